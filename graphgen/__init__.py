@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         u64p = ctypes.POINTER(ctypes.c_uint64)

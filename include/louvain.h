@@ -1,0 +1,195 @@
+/*
+ * louvain.h -- C ABI of the MI355X (gfx950) Louvain library.
+ *
+ * The library runs the two phases of the Louvain method for modularity
+ * maximisation -- local moving and aggregation -- on one GPU, as studied in
+ * "CPU vs. GPU for Community Detection: Performance Insights from GVE-Louvain
+ * and nu-Louvain" (Sahu, 2025).  References below name the paper's sections,
+ * equations and algorithms.
+ *
+ * Conventions shared by every entry point:
+ *  - Graphs are undirected, in symmetric CSR form: edge {i, j} with i != j is
+ *    stored as the arcs (i, j) and (j, i) with equal weight; a self-loop is one
+ *    arc (i, i).  Weights are positive integers.  W = sum of all arc weights is
+ *    the paper's 2m (Preliminaries).
+ *  - Pointers marked "device" must point to memory of the GPU current when the
+ *    handle is created; "host" pointers to ordinary host memory.  The library
+ *    never frees caller memory.
+ *  - Every call returns a louvain_status; the library never aborts the
+ *    process.  After a failure, louvain_last_error(handle) describes it.
+ *  - A handle is bound to one HIP stream and is not thread-safe.  Calls that
+ *    return results to the host synchronise that stream.
+ */
+#ifndef LOUVAIN_H
+#define LOUVAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct louvain_s louvain_t; /* opaque handle */
+
+typedef enum {
+    LOUVAIN_OK = 0,
+    LOUVAIN_ERR_INVALID = -1,   /* bad argument or malformed graph */
+    LOUVAIN_ERR_NOMEM = -2,     /* host allocation failed */
+    LOUVAIN_ERR_WORKSPACE = -3, /* workspace missing, misaligned or too small */
+    LOUVAIN_ERR_HIP = -4,       /* a HIP runtime call failed */
+    LOUVAIN_ERR_OVERFLOW = -5,  /* weights too large for the exact integer path */
+    LOUVAIN_ERR_STATE = -6      /* call out of order (e.g. membership before run) */
+} louvain_status;
+
+/* Local-moving semantics.
+ * ASYNC: one membership vector updated in place while vertices are processed
+ *   (the paper's GPU design, Algorithm 5, with Pick-Less every rho
+ *   iterations); nondeterministic order, reaches modularity close to the
+ *   sequential method.
+ * SYNC: every flagged vertex decides against the start-of-iteration state
+ *   (C', Sigma'); all moves are then applied together.  Deterministic: the
+ *   memberships, Sigma' and super-graphs are identical from run to run. */
+typedef enum { LOUVAIN_ASYNC = 0, LOUVAIN_SYNC = 1 } louvain_mode;
+
+/* Which vertices an iteration evaluates.
+ * NONE: all vertices every iteration.
+ * FLAGS: vertex pruning (Section 4.1, "Vertex pruning"): a vertex is evaluated
+ *   again only after a neighbour changed community. */
+typedef enum { LOUVAIN_PRUNE_NONE = 0, LOUVAIN_PRUNE_FLAGS = 1 } louvain_pruner;
+
+/* Input graph.  offsets: device, n+1 entries of int32 (offset_bits = 32) or
+ * int64 (offset_bits = 64), offsets[0] = 0, non-decreasing, offsets[n] = nnz.
+ * indices: device, nnz int32 in [0, n).  weights: device, nnz int32 > 0, or
+ * NULL for unit weights.  Requires n <= 2^31 - 2. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    int32_t offset_bits;
+    const void* offsets;
+    const int32_t* indices;
+    const int32_t* weights;
+} louvain_graph;
+
+/* Parameters; louvain_params_default() fills the paper's values
+ * (Section 4.3: 20 iterations per pass, 10 passes, tolerance 0.01 dropped
+ * 10x per pass, aggregation tolerance 0.8, Pick-Less every 4 iterations,
+ * vertex pruning). */
+typedef struct {
+    int32_t max_iterations;  /* per pass, >= 1 */
+    int32_t max_passes;      /* <= 0: until convergence */
+    int64_t tol_num;         /* initial tolerance tau_0 = tol_num / tol_den (>= 0) */
+    int64_t tol_den;         /* > 0 */
+    int64_t tol_drop;        /* tau_{p+1} = tau_p / tol_drop, >= 1 */
+    int64_t agg_num;         /* aggregation tolerance tau_agg = agg_num / agg_den: */
+    int64_t agg_den;         /*   stop when |Gamma| / |Gamma_old| > tau_agg */
+    int32_t pick_less;       /* rho: Pick-Less on when (t + rho/2) mod rho == 0; 0 = off */
+    int32_t mode;            /* louvain_mode */
+    int32_t pruner;          /* louvain_pruner */
+    int32_t validate;        /* 1: check offsets, indices and weights in create */
+    /* Degree-bucket overrides (0 = library default).  bucket_max_degree[b] is
+     * the largest degree handled by move bucket b; vertices above the last
+     * bucket use global-memory hash tables.  Used by tests to force paths. */
+    int32_t bucket_max_degree[8];
+    int32_t agg_bucket_max[8];
+    int32_t reserved[8];
+} louvain_params;
+
+/* Per-run counters, filled by louvain_get_stats after louvain_run. */
+typedef struct {
+    int32_t passes;             /* passes whose local-moving phase ran */
+    int32_t iterations;         /* local-moving iterations, all passes */
+    int64_t moves;              /* vertex moves applied */
+    int64_t communities;        /* final number of communities */
+    int64_t vertices_evaluated; /* vertex evaluations in the local-moving phase */
+    int64_t arcs_scanned;       /* arcs read by those evaluations */
+    int64_t distinct_scanned;   /* sum over evaluations of distinct neighbour communities */
+    double ms_total;            /* wall time of louvain_run */
+    double ms_move;             /* local-moving kernels (HIP events; profile_kernels only) */
+    double ms_aggregate;        /* aggregation kernels (HIP events; profile_kernels only) */
+    int32_t iterations_per_pass[32];
+    int64_t communities_per_pass[32];
+} louvain_stats;
+
+/* Per-kernel timing record (profiling mode). */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double ms;          /* summed HIP-event time of those launches */
+    int64_t alg_bytes;  /* algorithmic bytes moved by those launches */
+} louvain_kernel_stat;
+
+/* Trace callbacks (host memory; valid only during the call).
+ * iter_fn: after every local-moving iteration, the level's membership C'
+ *   (n ints) and community totals Sigma' (n int64), the number of moves and
+ *   the exact gain sum S of the iteration (Eq. (2) times W^2/2) as hi/lo.
+ * pass_fn: after every aggregation, the super-vertex graph in CSR form with
+ *   rows sorted by neighbour id (offsets int64[n+1], indices, weights int64). */
+typedef void (*louvain_iter_fn)(void* user, int32_t pass, int32_t iter, int64_t n, const int32_t* cprime,
+                                const int64_t* sigma, int64_t moves, int64_t gain_hi, uint64_t gain_lo);
+typedef void (*louvain_pass_fn)(void* user, int32_t pass, int64_t n, const int64_t* offsets,
+                                const int32_t* indices, const int64_t* weights, int32_t iterations);
+
+/* Fill p with the paper's defaults.  p: host, non-NULL. */
+void louvain_params_default(louvain_params* p);
+
+/* Bytes of device workspace the handle needs for this graph (upper bound
+ * over all passes).  g, p, bytes: host, non-NULL.  Only g->n, g->nnz,
+ * g->offset_bits and whether g->weights is NULL are read; no device access. */
+louvain_status louvain_workspace_size(const louvain_graph* g, const louvain_params* p, size_t* bytes);
+
+/* Create a handle for graph g on `stream` (a hipStream_t, NULL = default
+ * stream).  workspace: device, >= louvain_workspace_size bytes, 256-byte
+ * aligned, owned by the caller and borrowed until louvain_destroy, as are
+ * the graph arrays (they are not copied).  Computes W and the weighted
+ * degrees; with p->validate set, rejects malformed graphs with
+ * LOUVAIN_ERR_INVALID.  Returns LOUVAIN_ERR_OVERFLOW when W exceeds 2^62.
+ * out: host, receives the handle (NULL on failure). */
+louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, void* stream, void* workspace,
+                              size_t workspace_bytes, louvain_t** out);
+
+/* Run Louvain: the pass loop of Algorithm 1 / Algorithm 4 with the
+ * local-moving phase (Algorithm 2 / 5) and the aggregation phase
+ * (Algorithm 3 / 6).  Blocking: returns after the stream has drained.
+ * May be called again; each call starts from singleton communities. */
+louvain_status louvain_run(louvain_t* h);
+
+/* Copy the final membership to out: device, n int32.  Community ids are
+ * dense, 0 .. communities-1, numbered by ascending final label.
+ * LOUVAIN_ERR_STATE before the first successful louvain_run. */
+louvain_status louvain_get_membership(louvain_t* h, int32_t* out);
+
+/* Modularity of the final membership on the input graph, Eq. (1), computed
+ * on the GPU with exact integers: Q = num / den with num = sum_c (W*sigma_c -
+ * Sigma_c^2) and den = W^2 (den = 1 when W = 0).  q: host double (may be
+ * NULL); num, den: host int64[2] as {hi, lo bits} of a signed 128-bit
+ * integer (may be NULL). */
+louvain_status louvain_modularity(louvain_t* h, double* q, int64_t num[2], int64_t den[2]);
+
+/* Counters of the last run.  s: host. */
+louvain_status louvain_get_stats(louvain_t* h, louvain_stats* s);
+
+/* Enable (1) or disable (0) per-kernel HIP-event timing for later runs.
+ * Adds two event records per launch; off by default. */
+louvain_status louvain_set_profiling(louvain_t* h, int32_t enable);
+
+/* Copy up to max per-kernel records of the last run to out (host) and the
+ * record count to *count. */
+louvain_status louvain_get_kernel_stats(louvain_t* h, louvain_kernel_stat* out, int32_t max, int32_t* count);
+
+/* Install trace callbacks (either may be NULL).  Tracing copies state to the
+ * host after every iteration and pass; it is for testing, not speed. */
+louvain_status louvain_set_trace(louvain_t* h, louvain_iter_fn iter_fn, louvain_pass_fn pass_fn, void* user);
+
+/* Last error message of h (or of the last failed create when h is NULL).
+ * Never NULL; valid until the next call on h. */
+const char* louvain_last_error(const louvain_t* h);
+
+/* Release the handle (not the caller's graph or workspace).  NULL is ok. */
+void louvain_destroy(louvain_t* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOUVAIN_H */

@@ -62,7 +62,7 @@ _PASS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int6
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         lib.oracle_modularity.restype = ctypes.c_int

@@ -1,0 +1,300 @@
+"""Python binding of the gfx950 Louvain library (``lib/liblouvain_hip.so``).
+
+Every function mirrors an ``extern "C"`` entry point of ``include/louvain.h``
+under the same name and only marshals arguments; all computation runs in the
+HIP kernels.  PyTorch is used for device memory (tensors, the workspace) and
+for the current HIP stream.  There is no CPU fallback: when the library is not
+built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "liblouvain_hip.so")
+
+LOUVAIN_OK = 0
+LOUVAIN_ERR_INVALID = -1
+LOUVAIN_ERR_NOMEM = -2
+LOUVAIN_ERR_WORKSPACE = -3
+LOUVAIN_ERR_HIP = -4
+LOUVAIN_ERR_OVERFLOW = -5
+LOUVAIN_ERR_STATE = -6
+ASYNC = 0
+SYNC = 1
+PRUNE_NONE = 0
+PRUNE_FLAGS = 1
+
+EXPORTED = ["louvain_params_default", "louvain_workspace_size", "louvain_create", "louvain_run",
+            "louvain_get_membership", "louvain_modularity", "louvain_get_stats", "louvain_set_profiling",
+            "louvain_get_kernel_stats", "louvain_set_trace", "louvain_last_error", "louvain_destroy"]
+
+
+class LouvainGraph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("offset_bits", ctypes.c_int32),
+                ("offsets", ctypes.c_void_p), ("indices", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
+
+
+class LouvainParams(ctypes.Structure):
+    _fields_ = [("max_iterations", ctypes.c_int32), ("max_passes", ctypes.c_int32),
+                ("tol_num", ctypes.c_int64), ("tol_den", ctypes.c_int64), ("tol_drop", ctypes.c_int64),
+                ("agg_num", ctypes.c_int64), ("agg_den", ctypes.c_int64), ("pick_less", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("pruner", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("bucket_max_degree", ctypes.c_int32 * 8), ("agg_bucket_max", ctypes.c_int32 * 8),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class LouvainStats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("iterations", ctypes.c_int32), ("moves", ctypes.c_int64),
+                ("communities", ctypes.c_int64), ("vertices_evaluated", ctypes.c_int64),
+                ("arcs_scanned", ctypes.c_int64), ("distinct_scanned", ctypes.c_int64),
+                ("ms_total", ctypes.c_double), ("ms_move", ctypes.c_double), ("ms_aggregate", ctypes.c_double),
+                ("iterations_per_pass", ctypes.c_int32 * 32), ("communities_per_pass", ctypes.c_int64 * 32)]
+
+
+class LouvainKernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_int64)]
+
+
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+ITER_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _I32P, _I64P,
+                           ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64)
+PASS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, _I64P, _I32P, _I64P,
+                           ctypes.c_int32)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblouvain_hip.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.louvain_params_default.restype = None
+    lib.louvain_params_default.argtypes = [ctypes.POINTER(LouvainParams)]
+    lib.louvain_workspace_size.restype = ctypes.c_int
+    lib.louvain_workspace_size.argtypes = [ctypes.POINTER(LouvainGraph), ctypes.POINTER(LouvainParams),
+                                           ctypes.POINTER(sz)]
+    lib.louvain_create.restype = ctypes.c_int
+    lib.louvain_create.argtypes = [ctypes.POINTER(LouvainGraph), ctypes.POINTER(LouvainParams), vp, vp, sz,
+                                   ctypes.POINTER(vp)]
+    lib.louvain_run.restype = ctypes.c_int
+    lib.louvain_run.argtypes = [vp]
+    lib.louvain_get_membership.restype = ctypes.c_int
+    lib.louvain_get_membership.argtypes = [vp, vp]
+    lib.louvain_modularity.restype = ctypes.c_int
+    lib.louvain_modularity.argtypes = [vp, ctypes.POINTER(ctypes.c_double), _I64P, _I64P]
+    lib.louvain_get_stats.restype = ctypes.c_int
+    lib.louvain_get_stats.argtypes = [vp, ctypes.POINTER(LouvainStats)]
+    lib.louvain_set_profiling.restype = ctypes.c_int
+    lib.louvain_set_profiling.argtypes = [vp, ctypes.c_int32]
+    lib.louvain_get_kernel_stats.restype = ctypes.c_int
+    lib.louvain_get_kernel_stats.argtypes = [vp, ctypes.POINTER(LouvainKernelStat), ctypes.c_int32, _I32P]
+    lib.louvain_set_trace.restype = ctypes.c_int
+    lib.louvain_set_trace.argtypes = [vp, ITER_FN, PASS_FN, vp]
+    lib.louvain_last_error.restype = ctypes.c_char_p
+    lib.louvain_last_error.argtypes = [vp]
+    lib.louvain_destroy.restype = None
+    lib.louvain_destroy.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+class LouvainError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"louvain status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int, handle=None):
+    if status != LOUVAIN_OK:
+        msg = load_library().louvain_last_error(handle)
+        raise LouvainError(status, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------ thin wrappers
+
+def louvain_params_default() -> LouvainParams:
+    p = LouvainParams()
+    load_library().louvain_params_default(ctypes.byref(p))
+    return p
+
+
+def louvain_workspace_size(g: LouvainGraph, p: LouvainParams) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().louvain_workspace_size(ctypes.byref(g), ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def louvain_create(g: LouvainGraph, p: LouvainParams, stream: int, workspace: int, workspace_bytes: int):
+    h = ctypes.c_void_p()
+    _check(load_library().louvain_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(stream),
+                                         ctypes.c_void_p(workspace), workspace_bytes, ctypes.byref(h)))
+    return h
+
+
+def louvain_run(h) -> None:
+    _check(load_library().louvain_run(h), h)
+
+
+def louvain_get_membership(h, out_ptr: int) -> None:
+    _check(load_library().louvain_get_membership(h, ctypes.c_void_p(out_ptr)), h)
+
+
+def louvain_modularity(h):
+    """Returns (q, numerator, denominator) with exact Python ints."""
+    q = ctypes.c_double()
+    num = (ctypes.c_int64 * 2)()
+    den = (ctypes.c_int64 * 2)()
+    _check(load_library().louvain_modularity(h, ctypes.byref(q), num, den), h)
+
+    def i128(x):
+        return (int(x[0]) << 64) + (int(x[1]) & ((1 << 64) - 1))
+    return q.value, i128(num), i128(den)
+
+
+def louvain_get_stats(h) -> LouvainStats:
+    s = LouvainStats()
+    _check(load_library().louvain_get_stats(h, ctypes.byref(s)), h)
+    return s
+
+
+def louvain_set_profiling(h, enable: bool) -> None:
+    _check(load_library().louvain_set_profiling(h, int(enable)), h)
+
+
+def louvain_get_kernel_stats(h) -> list[dict]:
+    arr = (LouvainKernelStat * 64)()
+    cnt = ctypes.c_int32()
+    _check(load_library().louvain_get_kernel_stats(h, arr, 64, ctypes.byref(cnt)), h)
+    return [dict(name=arr[i].name.decode(), launches=arr[i].launches, ms=arr[i].ms, alg_bytes=arr[i].alg_bytes)
+            for i in range(min(cnt.value, 64))]
+
+
+def louvain_set_trace(h, iter_fn, pass_fn, user=None) -> None:
+    _check(load_library().louvain_set_trace(h, iter_fn or ITER_FN(), pass_fn or PASS_FN(), user), h)
+
+
+def louvain_last_error(h=None) -> str:
+    msg = load_library().louvain_last_error(h)
+    return msg.decode() if msg else ""
+
+
+def louvain_destroy(h) -> None:
+    if h:
+        load_library().louvain_destroy(h)
+
+
+# --------------------------------------------------------- torch plumbing
+
+class Louvain:
+    """A handle on one device-resident graph.
+
+    offsets/indices/weights are torch tensors on the current GPU (offsets
+    int32 or int64, indices int32, weights int32 or None for unit weights).
+    The workspace is a torch uint8 tensor; kernels run on the current stream.
+    """
+
+    def __init__(self, offsets, indices, weights=None, params: LouvainParams | None = None, **overrides):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU available: the Louvain library runs only on the GPU")
+        load_library()
+        self._keep = (offsets, indices, weights)
+        self.params = params or louvain_params_default()
+        for k, v in overrides.items():
+            if k in ("bucket_max_degree", "agg_bucket_max"):
+                arr = getattr(self.params, k)
+                for i, x in enumerate(v):
+                    arr[i] = x
+            else:
+                setattr(self.params, k, v)
+        n = offsets.numel() - 1
+        g = LouvainGraph()
+        g.n = n
+        g.nnz = indices.numel()
+        g.offset_bits = 64 if offsets.dtype == torch.int64 else 32
+        g.offsets = offsets.data_ptr()
+        g.indices = indices.data_ptr() if indices.numel() else 0
+        g.weights = weights.data_ptr() if weights is not None else None
+        self.graph = g
+        self.n = n
+        nbytes = louvain_workspace_size(g, self.params)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=offsets.device)
+        self.stream = torch.cuda.current_stream(offsets.device)
+        self.h = louvain_create(g, self.params, self.stream.cuda_stream, self.workspace.data_ptr(), nbytes)
+        self._cb = None
+
+    def run(self):
+        louvain_run(self.h)
+        return self
+
+    def membership(self):
+        import torch
+        out = torch.empty(self.n, dtype=torch.int32, device=self.workspace.device)
+        if self.n:
+            louvain_get_membership(self.h, out.data_ptr())
+        return out
+
+    def modularity(self):
+        return louvain_modularity(self.h)
+
+    def stats(self) -> LouvainStats:
+        return louvain_get_stats(self.h)
+
+    def set_profiling(self, enable: bool = True):
+        louvain_set_profiling(self.h, enable)
+
+    def kernel_stats(self):
+        return louvain_get_kernel_stats(self.h)
+
+    def trace(self, on_iter=None, on_pass=None):
+        """Install Python callbacks receiving numpy copies of each iteration's
+        (pass, iter, C', Sigma', moves, gain) and each pass's super-graph."""
+        import numpy as np
+
+        def it(_u, p, t, n, cp, sig, moves, ghi, glo):
+            if on_iter:
+                on_iter(int(p), int(t), np.ctypeslib.as_array(cp, shape=(n,)).copy() if n else np.zeros(0, np.int32),
+                        np.ctypeslib.as_array(sig, shape=(n,)).copy() if n else np.zeros(0, np.int64), int(moves),
+                        (int(ghi) << 64) + int(glo))
+
+        def pa(_u, p, n, off, idx, w, iters):
+            if on_pass:
+                o = np.ctypeslib.as_array(off, shape=(n + 1,)).copy()
+                m = int(o[-1])
+                ii = np.ctypeslib.as_array(idx, shape=(m,)).copy() if m else np.zeros(0, np.int32)
+                ww = np.ctypeslib.as_array(w, shape=(m,)).copy() if m else np.zeros(0, np.int64)
+                on_pass(int(p), int(n), o, ii, ww, int(iters))
+
+        self._cb = (ITER_FN(it), PASS_FN(pa))
+        louvain_set_trace(self.h, self._cb[0], self._cb[1])
+
+    def close(self):
+        if getattr(self, "h", None):
+            louvain_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def graph_tensors(g, device="cuda", offset_bits: int = 32, unit_weights: bool | None = None):
+    """Upload a graphgen.CSRGraph: returns (offsets, indices, weights-or-None)."""
+    import numpy as np
+    import torch
+    off = torch.from_numpy(np.ascontiguousarray(g.offsets, dtype=np.int64 if offset_bits == 64 else np.int32))
+    idx = torch.from_numpy(np.ascontiguousarray(g.indices, dtype=np.int32))
+    unit = bool(unit_weights) if unit_weights is not None else bool(g.weights.size == 0 or g.weights.max() == 1)
+    w = None if unit else torch.from_numpy(np.ascontiguousarray(g.weights, dtype=np.int32)).to(device)
+    return off.to(device), idx.to(device), w

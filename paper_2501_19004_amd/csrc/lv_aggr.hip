@@ -1,0 +1,506 @@
+// lv_aggr.hip -- aggregation phase, dendrogram lookup, modularity, validation.
+//
+// Aggregation (the paper's Algorithm 3 / Algorithm 6) merges each community
+// into one super-vertex: the super-arc (c, d) carries the summed weight of all
+// arcs (i, j) with C'[i] = c and C'[j] = d, self-loops included
+// (scanCommunities with self = true).  Steps here:
+//   used flags -> exclusive scan -> dense ids (renumber, ascending old id);
+//   community-vertex CSR by counting + scan + scatter;
+//   community total degree + scan -> "holey" row bounds;
+//   per community: hash (d, w) in an LDS table, bitonic-sort the table in
+//   LDS, write the sorted distinct entries into the holey row;
+//   large communities: a global-memory table, sorted in place;
+//   scan of distinct counts -> compacted, row-sorted super-graph CSR.
+#include <algorithm>
+
+#include "lv_internal.h"
+
+namespace lv {
+namespace {
+
+template <int N>
+struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
+template <>
+struct Log2<1> { static constexpr int v = 0; };
+template <typename T>
+struct TypeTag { using type = T; };
+template <int V>
+struct IntTag { static constexpr int value = V; };
+
+template <typename Fn>
+void dispatch_types(const LevelTypes& t, Fn&& fn) {
+    auto acc = [&](auto o, auto w) {
+        if (t.acc64) fn(o, w, TypeTag<u64>{});
+        else fn(o, w, TypeTag<uint32_t>{});
+    };
+    auto wk = [&](auto o) {
+        if (t.wk == 0) acc(o, IntTag<0>{});
+        else if (t.wk == 1) acc(o, IntTag<1>{});
+        else acc(o, IntTag<2>{});
+    };
+    if (t.off64) wk(TypeTag<int64_t>{});
+    else wk(TypeTag<int32_t>{});
+}
+
+inline unsigned blocks_for(int64_t items, int per_block) { return (unsigned)((items + per_block - 1) / per_block); }
+
+__device__ __forceinline__ void wave_count(bool want, int b, int32_t* count) {
+    const int lane = __lane_id();
+    u64 pending = __ballot(want);
+    while (pending) {
+        int leader = __ffsll((long long)pending) - 1;
+        int lb = __shfl(b, leader);
+        u64 same = __ballot(want && b == lb);
+        if (lane == leader) atomicAdd(&count[lb], __popcll(same));
+        pending &= ~same;
+    }
+}
+
+// Inclusive scan over a group of G lanes (G > 64: whole workgroup via LDS).
+template <int G>
+__device__ __forceinline__ i64 group_incl_scan(i64 v, i64* s_t) {
+    constexpr int GW = G < WAVE ? G : WAVE;
+    const int l = threadIdx.x % GW;
+#pragma unroll
+    for (int d = 1; d < GW; d <<= 1) {
+        i64 y = __shfl_up(v, d, GW);
+        if (l >= d) v += y;
+    }
+    if constexpr (G > WAVE) {
+        const int w = threadIdx.x / WAVE;
+        if (threadIdx.x % WAVE == WAVE - 1) s_t[w] = v;
+        __syncthreads();
+        i64 before = 0;
+        for (int k = 0; k < w; k++) before += s_t[k];
+        __syncthreads();
+        v += before;
+    }
+    return v;
+}
+template <int G>
+__device__ __forceinline__ i64 group_sum(i64 v, i64* s_t) {
+    constexpr int GW = G < WAVE ? G : WAVE;
+    v = group_sum64<GW>(v);
+    if constexpr (G > WAVE) {
+        const int w = threadIdx.x / WAVE;
+        if (threadIdx.x % WAVE == 0) s_t[w] = v;
+        __syncthreads();
+        v = 0;
+        for (int k = 0; k < G / WAVE; k++) v += s_t[k];
+        __syncthreads();
+    }
+    return v;
+}
+// Broadcast lane 0's value to the group.
+template <int G>
+__device__ __forceinline__ i64 group_bcast(i64 v, i64* s_t) {
+    if constexpr (G <= WAVE) {
+        return __shfl(v, 0, G);
+    } else {
+        if (threadIdx.x == 0) s_t[0] = v;
+        __syncthreads();
+        v = s_t[0];
+        __syncthreads();
+        return v;
+    }
+}
+
+// Feed every arc (j, w) of every member of community c into the table:
+// members are taken G at a time; their arc ranges are laid end to end and
+// the group strides over the concatenation (a lane finds its member by
+// binary search over the group's prefix of degrees).
+template <typename OffT, int WK, typename AccT, int G, typename InsertFn>
+__device__ __forceinline__ void feed_members(const Graph<OffT, WK>& g, const int32_t* __restrict__ Cp,
+                                             const int32_t* __restrict__ members, i64 m0, i64 m1, int lane,
+                                             i64* s_start, i64* s_pre, i64* s_t, InsertFn&& ins) {
+    for (i64 mb = m0; mb < m1; mb += G) {
+        i64 start = 0, deg = 0;
+        if (mb + lane < m1) {
+            const int32_t m = members[mb + lane];
+            start = (i64)g.off[m];
+            deg = (i64)g.off[m + 1] - start;
+        }
+        const i64 pre = group_incl_scan<G>(deg, s_t);
+        s_start[lane] = start;
+        s_pre[lane] = pre;
+        group_sync<G>();
+        const i64 total = s_pre[G - 1];
+        for (i64 f = lane; f < total; f += G) {
+            int lo = 0, hi = G - 1;  // first k with pre[k] > f
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pre[mid] > f) hi = mid; else lo = mid + 1;
+            }
+            const i64 e = s_start[lo] + (f - (lo ? s_pre[lo - 1] : 0));
+            ins(Cp[g.idx[e]], (AccT)g.weight(e));
+        }
+        group_sync<G>();
+    }
+}
+
+// In-place bitonic sort of CAP (key, value) pairs held by one group; keys
+// ascending, EMPTY_KEY last.
+template <int G, typename AccT>
+__device__ __forceinline__ void bitonic_sort_group(int32_t* keys, AccT* vals, int64_t cap, int lane) {
+    for (int64_t k = 2; k <= cap; k <<= 1) {
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            for (int64_t x = lane; x < cap; x += G) {
+                const int64_t y = x ^ j;
+                if (y > x) {
+                    const bool up = (x & k) == 0;
+                    const int32_t kx = keys[x], ky = keys[y];
+                    if ((kx > ky) == up) {
+                        keys[x] = ky; keys[y] = kx;
+                        const AccT t = vals[x]; vals[x] = vals[y]; vals[y] = t;
+                    }
+                }
+            }
+            group_sync<G>();
+        }
+    }
+}
+
+template <typename OffT, int WK, typename AccT, int G, int CAP>
+__global__ void __launch_bounds__(G > 256 ? G : 256) k_aggregate_lds(Graph<OffT, WK> g, AggArgs a,
+                                                                     const int32_t* __restrict__ list,
+                                                                     int32_t count) {
+    constexpr int BLOCK = G > 256 ? G : 256;
+    constexpr int NG = BLOCK / G;
+    constexpr int L2C = Log2<CAP>::v;
+    __shared__ int32_t s_keys[NG * CAP];
+    __shared__ AccT s_vals[NG * CAP];
+    __shared__ i64 s_start[NG * G], s_pre[NG * G];
+    __shared__ i64 s_t[BLOCK / WAVE];
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int64_t slot = (int64_t)blockIdx.x * NG + grp;
+    const bool active = slot < count;
+    const int32_t c = active ? list[slot] : 0;
+    int32_t* keys = s_keys + grp * CAP;
+    AccT* vals = s_vals + grp * CAP;
+    for (int s = lane; s < CAP; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }
+    group_sync<G>();
+    const i64 m0 = active ? a.coff[c] : 0, m1 = active ? a.coff[c + 1] : 0;
+    feed_members<OffT, WK, AccT, G>(g, a.Cp, a.members, m0, m1, lane, s_start + grp * G, s_pre + grp * G, s_t,
+                                    [&](int32_t d, AccT w) {
+                                        table_add<AccT>(keys, vals, CAP - 1, hash_slot<L2C>(d), d, w);
+                                    });
+    i64 L = 0;
+    for (int s = lane; s < CAP; s += G) L += keys[s] != EMPTY_KEY;
+    L = group_sum<G>(L, s_t);
+    bitonic_sort_group<G, AccT>(keys, vals, CAP, lane);
+    if (active) {
+        const i64 h = a.hoff[c];
+        for (i64 x = lane; x < L; x += G) {
+            a.hidx[h + x] = keys[x];
+            if (a.out_w64) ((i64*)a.hw)[h + x] = (i64)vals[x];
+            else ((int32_t*)a.hw)[h + x] = (int32_t)vals[x];
+        }
+        if (lane == 0) a.rowlen[c] = (int32_t)L;
+    }
+}
+
+// Large communities: one 1024-thread workgroup, table in the global pool
+// (capacity >= 2 * bound, power of two), sorted in place after hashing.
+template <typename OffT, int WK, typename AccT>
+__global__ void __launch_bounds__(1024) k_aggregate_hub(Graph<OffT, WK> g, AggArgs a,
+                                                        const int32_t* __restrict__ list, int32_t count) {
+    constexpr int G = 1024;
+    __shared__ i64 s_start[G], s_pre[G];
+    __shared__ i64 s_t[G / WAVE];
+    const int64_t slot = blockIdx.x;
+    if (slot >= count) return;
+    const int32_t c = list[slot];
+    const int lane = threadIdx.x;
+    const int64_t toff = a.hub_off[slot] - a.hub_base;
+    const int64_t cap = a.hub_off[slot + 1] - a.hub_off[slot];
+    const int log2cap = __ffsll((long long)cap) - 1;
+    int32_t* keys = a.hub_keys + toff;
+    AccT* vals = (AccT*)a.hub_vals + toff;
+    for (int64_t s = lane; s < cap; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }
+    __syncthreads();
+    feed_members<OffT, WK, AccT, G>(g, a.Cp, a.members, a.coff[c], a.coff[c + 1], lane, s_start, s_pre, s_t,
+                                    [&](int32_t d, AccT w) {
+                                        table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap),
+                                                        d, w);
+                                    });
+    i64 L = 0;
+    for (int64_t s = lane; s < cap; s += G) L += keys[s] != EMPTY_KEY;
+    L = group_sum<G>(L, s_t);
+    bitonic_sort_group<G, AccT>(keys, vals, cap, lane);
+    const i64 h = a.hoff[c];
+    for (i64 x = lane; x < L; x += G) {
+        a.hidx[h + x] = keys[x];
+        if (a.out_w64) ((i64*)a.hw)[h + x] = (i64)vals[x];
+        else ((int32_t*)a.hw)[h + x] = (int32_t)vals[x];
+    }
+    if (lane == 0) a.rowlen[c] = (int32_t)L;
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void k_mark_used(const int32_t* __restrict__ Cp, int64_t n, int32_t* __restrict__ used) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) used[Cp[v]] = 1;
+}
+__global__ void k_relabel(int32_t* __restrict__ Cp, int64_t n, const int32_t* __restrict__ newid) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) Cp[v] = newid[Cp[v]];
+}
+__global__ void k_dendrogram(int32_t* __restrict__ C, int64_t n0, const int32_t* __restrict__ Cp) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n0) C[v] = Cp[C[v]];
+}
+__global__ void k_final_lookup(int32_t* __restrict__ C, int64_t n0, const int32_t* __restrict__ Cp,
+                               const int32_t* __restrict__ newid) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n0) C[v] = newid[Cp[C[v]]];
+}
+template <typename OffT>
+__global__ void k_comm_count(const OffT* __restrict__ off, int64_t n, const int32_t* __restrict__ Cp,
+                             int32_t* __restrict__ cnt, int64_t* __restrict__ cdeg) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = Cp[v];
+    atomicAdd(&cnt[c], 1);
+    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+    if (deg) atomicAdd((u64*)&cdeg[c], (u64)deg);
+}
+__global__ void k_comm_fill(int64_t n, const int32_t* __restrict__ Cp, const int32_t* __restrict__ coff,
+                            int32_t* __restrict__ cursor, int32_t* __restrict__ members) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = Cp[v];
+    members[coff[c] + atomicAdd(&cursor[c], 1)] = (int32_t)v;
+}
+__global__ void k_agg_classify(int64_t ncom, const int64_t* __restrict__ hoff, int64_t bound_cap, Buckets B,
+                               uint8_t* __restrict__ cbucket, int32_t* __restrict__ rowlen, Ctl* ctl) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int b = 255;
+    if (c < ncom) {
+        int64_t bound = hoff[c + 1] - hoff[c];
+        bound = bound < bound_cap ? bound : bound_cap;
+        if (bound > 0) {
+            b = B.nb;
+            for (int k = 0; k < B.nb; k++)
+                if (bound <= B.maxdeg[k]) { b = k; break; }
+        }
+        cbucket[c] = (uint8_t)b;
+        rowlen[c] = 0;
+    }
+    wave_count(c < ncom && b != 255, b, ctl->bcount);
+}
+__global__ void k_agg_fill(int64_t ncom, const uint8_t* __restrict__ cbucket, int32_t* __restrict__ alist,
+                           const int64_t* __restrict__ seg, Ctl* ctl) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = c < ncom ? cbucket[c] : 255;
+    wave_enqueue(b != 255, b, (int32_t)c, alist, seg, ctl->bcursor);
+}
+__global__ void k_agg_caps(const int32_t* __restrict__ list, int32_t count, const int64_t* __restrict__ hoff,
+                           int64_t bound_cap, int64_t* __restrict__ caps) {
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= count) return;
+    const int32_t c = list[h];
+    int64_t bound = hoff[c + 1] - hoff[c];
+    bound = bound < bound_cap ? bound : bound_cap;
+    uint64_t cap = 1;
+    while (cap < 2 * (uint64_t)bound) cap <<= 1;
+    caps[h] = (int64_t)cap;
+}
+
+// Copy each holey row to its compacted position; 32 lanes per row.
+template <typename GOffT>
+__global__ void __launch_bounds__(256) k_compact(int64_t ncom, const int64_t* __restrict__ hoff,
+                                                 const int32_t* __restrict__ hidx, const void* __restrict__ hw,
+                                                 const GOffT* __restrict__ goff, int32_t* __restrict__ gidx,
+                                                 void* __restrict__ gw, int w64) {
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 32;
+    const int lane = threadIdx.x % 32;
+    if (c >= ncom) return;
+    const int64_t src = hoff[c], dst = (int64_t)goff[c], len = (int64_t)goff[c + 1] - dst;
+    for (int64_t x = lane; x < len; x += 32) {
+        gidx[dst + x] = hidx[src + x];
+        if (w64) ((i64*)gw)[dst + x] = ((const i64*)hw)[src + x];
+        else ((int32_t*)gw)[dst + x] = ((const int32_t*)hw)[src + x];
+    }
+}
+
+// Modularity pieces on the input graph: sigma_c (arcs inside c) and Sigma_c.
+template <typename OffT, int WK>
+__global__ void __launch_bounds__(256) k_mod_arcs(Graph<OffT, WK> g, int64_t n, const int32_t* __restrict__ C,
+                                                  i64* __restrict__ sigin, i64* __restrict__ sigtot) {
+    const int lane = threadIdx.x % WAVE;
+    const int64_t nw = (int64_t)gridDim.x * (256 / WAVE);
+    for (int64_t v = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE; v < n; v += nw) {
+        const int32_t cv = C[v];
+        i64 in = 0, tot = 0;
+        for (i64 e = (i64)g.off[v] + lane; e < (i64)g.off[v + 1]; e += WAVE) {
+            const i64 w = g.weight(e);
+            tot += w;
+            if (C[g.idx[e]] == cv) in += w;
+        }
+        in = group_sum64<WAVE>(in);
+        tot = group_sum64<WAVE>(tot);
+        if (lane == 0 && tot) {
+            atomicAdd((u64*)&sigtot[cv], (u64)tot);
+            if (in) atomicAdd((u64*)&sigin[cv], (u64)in);
+        }
+    }
+}
+__global__ void __launch_bounds__(256) k_mod_terms(int64_t ncom, i64 W, const i64* __restrict__ sigin,
+                                                   const i64* __restrict__ sigtot, Ctl* ctl) {
+    __shared__ i128 s_part[256 / WAVE];
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    i128 t = 0;
+    if (c < ncom) t = (i128)W * sigin[c] - (i128)sigtot[c] * sigtot[c];
+    // wave reduction of 128-bit values
+    for (int m = WAVE / 2; m >= 1; m >>= 1) t += shfl_xor128(t, m, WAVE);
+    if (threadIdx.x % WAVE == 0) s_part[threadIdx.x / WAVE] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        i128 s = 0;
+        for (int k = 0; k < 256 / WAVE; k++) s += s_part[k];
+        if (s != 0) atomic_add_i128(&ctl->q_lo, &ctl->q_hi, s);
+    }
+}
+
+// Validation: offsets monotone, indices in range, weights positive; sums W.
+template <typename OffT, int WK>
+__global__ void __launch_bounds__(256) k_validate(Graph<OffT, WK> g, int64_t n, int64_t nnz, int check, Ctl* ctl) {
+    const int lane = threadIdx.x % WAVE;
+    const int64_t nw = (int64_t)gridDim.x * (256 / WAVE);
+    u64 wsum = 0;
+    int err = 0;
+    for (int64_t v = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE; v < n; v += nw) {
+        const i64 o0 = (i64)g.off[v], o1 = (i64)g.off[v + 1];
+        if (check && (o1 < o0 || o0 < 0 || o1 > nnz)) { err |= 1; continue; }
+        for (i64 e = o0 + lane; e < o1; e += WAVE) {
+            const i64 w = g.weight(e);
+            if (check) {
+                const int32_t j = g.idx[e];
+                if (j < 0 || j >= n) err |= 2;
+                if (w <= 0) err |= 4;
+            }
+            wsum += (u64)w;
+        }
+    }
+    wsum = (u64)group_sum64<WAVE>((i64)wsum);
+    if (lane == 0 && wsum) atomicAdd(&ctl->wsum, wsum);
+    if (err) atomicOr(&ctl->err, err);
+}
+
+}  // namespace
+
+void launch_mark_used(const int32_t* Cp, int64_t n, int32_t* used, hipStream_t s) {
+    if (n > 0) k_mark_used<<<blocks_for(n, 256), 256, 0, s>>>(Cp, n, used);
+}
+void launch_relabel(int32_t* Cp, int64_t n, const int32_t* newid, hipStream_t s) {
+    if (n > 0) k_relabel<<<blocks_for(n, 256), 256, 0, s>>>(Cp, n, newid);
+}
+void launch_dendrogram(int32_t* C, int64_t n0, const int32_t* Cp, hipStream_t s) {
+    if (n0 > 0) k_dendrogram<<<blocks_for(n0, 256), 256, 0, s>>>(C, n0, Cp);
+}
+void launch_final_lookup(int32_t* C, int64_t n0, const int32_t* Cp, const int32_t* newid, hipStream_t s) {
+    if (n0 > 0) k_final_lookup<<<blocks_for(n0, 256), 256, 0, s>>>(C, n0, Cp, newid);
+}
+void launch_comm_count(const LevelView& L, const int32_t* Cp, int32_t* cnt, int64_t* cdeg, hipStream_t s) {
+    if (L.n <= 0) return;
+    if (L.t.off64)
+        k_comm_count<int64_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, Cp, cnt, cdeg);
+    else
+        k_comm_count<int32_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, Cp, cnt, cdeg);
+}
+void launch_comm_fill(int64_t n, const int32_t* Cp, const int32_t* coff, int32_t* cursor, int32_t* members,
+                      hipStream_t s) {
+    if (n > 0) k_comm_fill<<<blocks_for(n, 256), 256, 0, s>>>(n, Cp, coff, cursor, members);
+}
+void launch_agg_classify(int64_t ncom, const int64_t* hoff, int64_t bound_cap, const Buckets& B, uint8_t* cbucket,
+                         int32_t* rowlen, Ctl* ctl, hipStream_t s) {
+    if (ncom > 0) k_agg_classify<<<blocks_for(ncom, 256), 256, 0, s>>>(ncom, hoff, bound_cap, B, cbucket, rowlen, ctl);
+}
+void launch_agg_fill(int64_t ncom, const uint8_t* cbucket, int32_t* alist, const int64_t* seg, Ctl* ctl,
+                     hipStream_t s) {
+    if (ncom > 0) k_agg_fill<<<blocks_for(ncom, 256), 256, 0, s>>>(ncom, cbucket, alist, seg, ctl);
+}
+void launch_agg_caps(const int32_t* list, int32_t count, const int64_t* hoff, int64_t bound_cap, int64_t* caps,
+                     hipStream_t s) {
+    if (count > 0) k_agg_caps<<<blocks_for(count, 256), 256, 0, s>>>(list, count, hoff, bound_cap, caps);
+}
+
+void launch_aggregate(const LevelView& L, int bucket, const AggArgs& a, const int32_t* list, int32_t count,
+                      hipStream_t s) {
+    if (count <= 0) return;
+    dispatch_types(L.t, [&](auto o, auto w, auto ac) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        using AccT = typename decltype(ac)::type;
+        Graph<OffT, WK> g{(const OffT*)L.off, L.idx, L.w};
+        auto go = [&](auto btag) {
+            constexpr int b = decltype(btag)::value;
+            constexpr int G = AGG_G[b], CAP = AGG_CAP[b];
+            constexpr int BLOCK = G > 256 ? G : 256;
+            k_aggregate_lds<OffT, WK, AccT, G, CAP><<<blocks_for(count, BLOCK / G), BLOCK, 0, s>>>(g, a, list, count);
+        };
+        switch (bucket) {
+            case 0: go(IntTag<0>{}); break;
+            case 1: go(IntTag<1>{}); break;
+            case 2: go(IntTag<2>{}); break;
+            default: go(IntTag<3>{}); break;
+        }
+    });
+}
+
+void launch_aggregate_hub(const LevelView& L, const AggArgs& a, const int32_t* list, int32_t count, hipStream_t s) {
+    if (count <= 0) return;
+    dispatch_types(L.t, [&](auto o, auto w, auto ac) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        using AccT = typename decltype(ac)::type;
+        Graph<OffT, WK> g{(const OffT*)L.off, L.idx, L.w};
+        k_aggregate_hub<OffT, WK, AccT><<<(unsigned)count, 1024, 0, s>>>(g, a, list, count);
+    });
+}
+
+void launch_compact(int64_t ncom, const int64_t* hoff, const int32_t* hidx, const void* hw, const void* goff,
+                    int goff64, int32_t* gidx, void* gw, int w64, hipStream_t s) {
+    if (ncom <= 0) return;
+    const unsigned grid = blocks_for(ncom * 32, 256);
+    if (goff64)
+        k_compact<int64_t><<<grid, 256, 0, s>>>(ncom, hoff, hidx, hw, (const int64_t*)goff, gidx, gw, w64);
+    else
+        k_compact<int32_t><<<grid, 256, 0, s>>>(ncom, hoff, hidx, hw, (const int32_t*)goff, gidx, gw, w64);
+}
+
+void launch_rowlen_to_offsets(const int32_t* rowlen, int64_t ncom, void* goff, int goff64, void* scratch,
+                              hipStream_t s) {
+    if (goff64) scan_i32_to_i64(rowlen, (int64_t*)goff, ncom, scratch, s);
+    else scan_i32_to_i32(rowlen, (int32_t*)goff, ncom, scratch, s);
+}
+
+void launch_modularity(const LevelView& L0, const int32_t* C, int64_t ncom, i64 W, i64* sigin, i64* sigtot,
+                       Ctl* ctl, hipStream_t s) {
+    if (L0.n <= 0) return;
+    LevelTypes t = L0.t;
+    t.acc64 = 0;
+    dispatch_types(t, [&](auto o, auto w, auto) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        Graph<OffT, WK> g{(const OffT*)L0.off, L0.idx, L0.w};
+        const unsigned grid = (unsigned)std::min<int64_t>(16384, (L0.n + 3) / 4);
+        k_mod_arcs<OffT, WK><<<grid, 256, 0, s>>>(g, L0.n, C, sigin, sigtot);
+    });
+    if (ncom > 0) k_mod_terms<<<blocks_for(ncom, 256), 256, 0, s>>>(ncom, W, sigin, sigtot, ctl);
+}
+
+void launch_validate(const LevelView& L, int check, Ctl* ctl, hipStream_t s) {
+    if (L.n <= 0) return;
+    LevelTypes t = L.t;
+    t.acc64 = 0;
+    dispatch_types(t, [&](auto o, auto w, auto) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        Graph<OffT, WK> g{(const OffT*)L.off, L.idx, L.w};
+        const unsigned grid = (unsigned)std::min<int64_t>(16384, (L.n + 3) / 4);
+        k_validate<OffT, WK><<<grid, 256, 0, s>>>(g, L.n, L.nnz, check, ctl);
+    });
+}
+
+}  // namespace lv

@@ -1,0 +1,890 @@
+// lv_api.cpp -- C ABI and host driver of the gfx950 Louvain library.
+//
+// The driver is the pass loop of the paper's Algorithm 1 / Algorithm 4:
+//   per pass: K' = row sums, Sigma' = K', C' = identity, all vertices queued;
+//   local moving until the iteration's gain sum S satisfies
+//     2*S / W^2 <= tau_p = tau_0 / drop^p   (tested exactly in integers)
+//   or MAX_ITERATIONS; stop if that took <= 1 iteration; count communities;
+//   stop if none merged or |Gamma| / |Gamma_old| > tau_agg; renumber;
+//   dendrogram lookup; aggregate; next pass.
+//   After the loop: final lookup when it stopped before aggregating.
+// Community counts for the shrink test cover vertices with at least one arc.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "louvain.h"
+#include "lv_internal.h"
+
+using namespace lv;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+inline uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Layout {
+    size_t ctl, seg, C, Cp, K, Sig, mark, vbucket, blist, qa, qb, movers, hcaps, hpre;
+    size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
+    size_t hidx, hw, sup_off[2], sup_idx[2], sup_w[2], pool_keys, pool_vals, scan;
+    int64_t pool_entries;
+    size_t total;
+};
+
+bool make_layout(int64_t n, int64_t m, Layout* L) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes > 0 ? bytes : 1); return at; };
+    const size_t N = (size_t)n, M = (size_t)m;
+    L->ctl = take(sizeof(Ctl));
+    L->seg = take(32 * sizeof(int64_t));
+    L->C = take(N * 4);
+    L->Cp = take(N * 4);
+    L->K = take(N * 8);
+    L->Sig = take(N * 8);
+    L->mark = take(N * 4);
+    L->vbucket = take(N);
+    L->blist = take(N * 4);
+    L->qa = take(N * 4);
+    L->qb = take(N * 4);
+    L->movers = take(2 * N * 4);
+    L->hcaps = take((N + 1) * 8);
+    L->hpre = take((N + 1) * 8);
+    L->used = take((N + 1) * 4);
+    L->newid = take((N + 1) * 4);
+    L->cnt = take((N + 1) * 4);
+    L->coff = take((N + 1) * 4);
+    L->cursor = take(N * 4);
+    L->members = take(N * 4);
+    L->cdeg = take((N + 1) * 8);
+    L->hoff = take((N + 1) * 8);
+    L->cbucket = take(N);
+    L->alist = take(N * 4);
+    L->rowlen = take((N + 1) * 4);
+    L->hidx = take(M * 4);
+    L->hw = take(M * 8);
+    for (int k = 0; k < 2; k++) {
+        L->sup_off[k] = take((N + 1) * 8);
+        L->sup_idx[k] = take(M * 4);
+        L->sup_w[k] = take(M * 8);
+    }
+    int64_t pool = (int64_t)next_pow2(2 * (uint64_t)(n + 1));
+    int64_t want = std::min<int64_t>(std::max<int64_t>(2 * m, (int64_t)1 << 20), (int64_t)1 << 28);
+    pool = std::max(pool, want);
+    L->pool_entries = pool;
+    L->pool_keys = take((size_t)pool * 4);
+    L->pool_vals = take((size_t)pool * 8);
+    L->scan = take(scan_scratch_bytes(n + 2));
+    L->total = o;
+    return true;
+}
+
+struct KRec {
+    int kind;  // index into kernel name table
+    hipEvent_t e0, e1;
+    int64_t bytes;
+};
+
+enum KName { K_MOVE0 = 0, K_MOVE1, K_MOVE2, K_MOVE3, K_MOVE4, K_MOVE_HUB, K_SYNC_APPLY, K_PASS_INIT, K_AGG_PREP,
+             K_AGG0, K_AGG1, K_AGG2, K_AGG3, K_AGG_HUB, K_COMPACT, K_COUNT };
+const char* KNAMES[K_COUNT] = {"move_b0", "move_b1", "move_b2", "move_b3", "move_b4", "move_hub", "sync_apply",
+                               "pass_init", "aggregate_prep", "aggregate_b0", "aggregate_b1", "aggregate_b2",
+                               "aggregate_b3", "aggregate_hub", "compact"};
+
+}  // namespace
+
+struct louvain_s {
+    hipStream_t stream = nullptr;
+    louvain_graph g{};
+    louvain_params p{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay{};
+    LevelView L0;
+    int64_t W = 0;
+    int sup_off64 = 0, sup_wk = 1;
+    bool ran = false;
+    int64_t ncom = 0;
+    louvain_stats st{};
+    std::string err = "no error";
+    void* pinned = nullptr;  // readback staging
+    void* pinned_up = nullptr;  // upload staging
+    louvain_iter_fn itfn = nullptr;
+    louvain_pass_fn pafn = nullptr;
+    void* user = nullptr;
+    bool prof = false;
+    std::vector<KRec> recs;
+    std::vector<hipEvent_t> evpool;
+    size_t evnext = 0;
+    double kms[K_COUNT] = {};
+    int64_t klaunch[K_COUNT] = {};
+    int64_t kbytes[K_COUNT] = {};
+    uint32_t stamp = 0;
+    Buckets mb{}, ab{};
+
+    template <typename T>
+    T* at(size_t off) { return (T*)(ws + off); }
+    Ctl* ctl() { return at<Ctl>(lay.ctl); }
+};
+
+namespace {
+
+louvain_status fail(louvain_t* h, louvain_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_create_error = buf;
+    return st;
+}
+
+#define HIPCHK(h, x)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((h), LOUVAIN_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_));     \
+    } while (0)
+
+hipEvent_t next_event(louvain_t* h) {
+    if (h->evnext >= h->evpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->evpool.push_back(e);
+    }
+    return h->evpool[h->evnext++];
+}
+
+// Time the launches issued by fn() under kernel name `kind` (profiling mode).
+template <typename Fn>
+void timed(louvain_t* h, int kind, int64_t bytes, Fn&& fn) {
+    if (!h->prof) { fn(); return; }
+    hipEvent_t a = next_event(h), b = next_event(h);
+    if (!a || !b) { fn(); return; }
+    hipEventRecord(a, h->stream);
+    fn();
+    hipEventRecord(b, h->stream);
+    h->recs.push_back({kind, a, b, bytes});
+}
+
+louvain_status readback(louvain_t* h, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return LOUVAIN_OK;
+    if (bytes <= (1 << 20)) {
+        HIPCHK(h, hipMemcpyAsync(h->pinned, src, bytes, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        memcpy(dst, h->pinned, bytes);
+    } else {
+        HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    return LOUVAIN_OK;
+}
+
+Buckets make_buckets(const int32_t* over, int nb, const int* caps, const int* defaults) {
+    Buckets B{};
+    B.nb = nb;
+    for (int k = 0; k < nb; k++) {
+        int v = over[k];
+        if (v == 0) v = defaults[k];
+        else if (v < 0) v = 0;                 // bucket disabled
+        B.maxdeg[k] = std::min(v, caps[k] / 2);
+    }
+    return B;
+}
+
+bool converged(unsigned __int128 S, int64_t W, const louvain_params& p, int pass) {
+    // 2*S*tol_den*drop^pass <= tol_num * W^2, exactly
+    unsigned __int128 rhs = (unsigned __int128)p.tol_num * ((unsigned __int128)W * (unsigned __int128)W);
+    unsigned __int128 lhs = 2 * S * (unsigned __int128)p.tol_den;
+    for (int k = 0; k < pass; k++) {
+        if (lhs > rhs) return false;
+        lhs *= (unsigned __int128)p.tol_drop;
+    }
+    return lhs <= rhs;
+}
+
+// Bytes of algorithmic traffic of one evaluation batch (see the roofline model).
+int64_t move_alg_bytes(const LevelView& L, uint64_t eval, uint64_t arcs, uint64_t distinct, uint64_t moves,
+                       uint64_t marcs, int sync) {
+    const int64_t offb = L.t.off64 ? 8 : 4;
+    const int64_t wb = L.t.wk == 0 ? 0 : (L.t.wk == 1 ? 4 : 8);
+    int64_t b = (int64_t)eval * (4 + 4 + 8 + 8 + 2 * offb) + (int64_t)arcs * (4 + 4 + wb) + (int64_t)distinct * 8;
+    if (sync) b += (int64_t)moves * 8;
+    else b += (int64_t)moves * (4 + 16) + (int64_t)marcs * (4 + 4 + 1);
+    return b;
+}
+
+struct IterRead {
+    u64 s_lo, s_hi, moves, pad0, pad1, pad2;
+    int32_t qcount[MAX_BUCKETS];
+    int32_t movers, err;
+};
+
+}  // namespace
+
+extern "C" {
+
+void louvain_params_default(louvain_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->max_iterations = 20;
+    p->max_passes = 10;
+    p->tol_num = 1;
+    p->tol_den = 100;
+    p->tol_drop = 10;
+    p->agg_num = 4;
+    p->agg_den = 5;
+    p->pick_less = 4;
+    p->mode = LOUVAIN_ASYNC;
+    p->pruner = LOUVAIN_PRUNE_FLAGS;
+    p->validate = 1;
+}
+
+louvain_status louvain_workspace_size(const louvain_graph* g, const louvain_params* p, size_t* bytes) {
+    if (!g || !p || !bytes) return fail(nullptr, LOUVAIN_ERR_INVALID, "null argument");
+    if (g->n < 0 || g->nnz < 0 || g->n > 0x7ffffffeLL)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "n must be in [0, 2^31-2] and nnz >= 0");
+    Layout L;
+    make_layout(g->n, g->nnz, &L);
+    *bytes = L.total;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, void* stream, void* workspace,
+                              size_t workspace_bytes, louvain_t** out) {
+    if (!out) return fail(nullptr, LOUVAIN_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!g || !p) return fail(nullptr, LOUVAIN_ERR_INVALID, "null graph or params");
+    if (g->n < 0 || g->nnz < 0 || g->n > 0x7ffffffeLL)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "n must be in [0, 2^31-2] and nnz >= 0");
+    if (g->offset_bits != 32 && g->offset_bits != 64)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "offset_bits must be 32 or 64");
+    if (g->offset_bits == 32 && g->nnz > 0x7fffffffLL)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "nnz too large for 32-bit offsets");
+    if (!g->offsets || (g->nnz > 0 && !g->indices))
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "offsets/indices missing");
+    if (p->max_iterations < 1 || p->tol_den <= 0 || p->tol_num < 0 || p->tol_drop < 1 || p->agg_den <= 0 ||
+        p->agg_num < 0 || p->pick_less < 0 || (p->mode != LOUVAIN_ASYNC && p->mode != LOUVAIN_SYNC) ||
+        (p->pruner != LOUVAIN_PRUNE_NONE && p->pruner != LOUVAIN_PRUNE_FLAGS))
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid parameter value");
+    Layout lay;
+    make_layout(g->n, g->nnz, &lay);
+    if (!workspace || workspace_bytes < lay.total || ((uintptr_t)workspace % ALIGN) != 0)
+        return fail(nullptr, LOUVAIN_ERR_WORKSPACE, "workspace must be %zu bytes, 256-byte aligned (got %zu)",
+                    lay.total, workspace_bytes);
+
+    louvain_t* h = new (std::nothrow) louvain_s();
+    if (!h) return fail(nullptr, LOUVAIN_ERR_NOMEM, "handle allocation failed");
+    h->stream = (hipStream_t)stream;
+    h->g = *g;
+    h->p = *p;
+    h->ws = (char*)workspace;
+    h->ws_bytes = workspace_bytes;
+    h->lay = lay;
+    h->L0.n = g->n;
+    h->L0.nnz = g->nnz;
+    h->L0.off = g->offsets;
+    h->L0.idx = g->indices;
+    h->L0.w = g->weights;
+    h->L0.t.off64 = g->offset_bits == 64;
+    h->L0.t.wk = g->weights ? 1 : 0;
+    h->L0.t.acc64 = 0;
+    h->mb = make_buckets(p->bucket_max_degree, NB_MOVE, MOVE_CAP, MOVE_DEFAULT_MAX);
+    h->ab = make_buckets(p->agg_bucket_max, NB_AGG, AGG_CAP, AGG_DEFAULT_MAX);
+    auto bail = [&](louvain_status st) {
+        g_create_error = h->err;
+        louvain_destroy(h);
+        return st;
+    };
+    if (hipHostMalloc(&h->pinned, 1 << 20, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&h->pinned_up, 1 << 16, hipHostMallocDefault) != hipSuccess) {
+        h->err = "pinned host allocation failed";
+        return bail(LOUVAIN_ERR_HIP);
+    }
+    // zero control block and pruning stamps
+    if (hipMemsetAsync(h->ctl(), 0, sizeof(Ctl), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->at<uint32_t>(lay.mark), 0, (size_t)std::max<int64_t>(g->n, 1) * 4, h->stream) !=
+            hipSuccess) {
+        h->err = "workspace initialisation failed";
+        return bail(LOUVAIN_ERR_HIP);
+    }
+    // endpoints of the offsets array
+    if (g->n >= 0) {
+        int64_t ends[2] = {0, 0};
+        const size_t ob = g->offset_bits / 8;
+        char tmp[16] = {};
+        if (hipMemcpyAsync(tmp, g->offsets, ob, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipMemcpyAsync(tmp + 8, (const char*)g->offsets + ob * g->n, ob, hipMemcpyDeviceToHost, h->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess) {
+            h->err = "cannot read offsets";
+            return bail(LOUVAIN_ERR_HIP);
+        }
+        if (ob == 4) { ends[0] = *(int32_t*)tmp; ends[1] = *(int32_t*)(tmp + 8); }
+        else { ends[0] = *(int64_t*)tmp; ends[1] = *(int64_t*)(tmp + 8); }
+        if (ends[0] != 0 || ends[1] != g->nnz) {
+            h->err = "offsets[0] must be 0 and offsets[n] must equal nnz";
+            return bail(LOUVAIN_ERR_INVALID);
+        }
+    }
+    // total weight (and validation)
+    launch_validate(h->L0, p->validate ? 1 : 0, h->ctl(), h->stream);
+    Ctl c;
+    if (readback(h, &c, h->ctl(), sizeof(Ctl)) != LOUVAIN_OK) return bail(LOUVAIN_ERR_HIP);
+    if (c.err) {
+        h->err = std::string("invalid graph:") + ((c.err & 1) ? " offsets not monotone" : "") +
+                 ((c.err & 2) ? " index out of range" : "") + ((c.err & 4) ? " non-positive weight" : "");
+        return bail(LOUVAIN_ERR_INVALID);
+    }
+    h->W = (int64_t)c.wsum;
+    if (c.wsum > ((u64)1 << 62)) {
+        h->err = "total weight exceeds 2^62";
+        return bail(LOUVAIN_ERR_OVERFLOW);
+    }
+    h->sup_off64 = g->nnz > 0x7fffffffLL;
+    h->sup_wk = h->W < 0x7fffffffLL ? 1 : 2;
+    *out = h;
+    return LOUVAIN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Runner {
+    louvain_t* h;
+    hipStream_t s;
+    louvain_status st = LOUVAIN_OK;
+    std::vector<int64_t> hub_pre;
+
+    explicit Runner(louvain_t* hh) : h(hh), s(hh->stream) {}
+
+    Ctl* ctl() { return h->ctl(); }
+    template <typename T>
+    T* at(size_t off) { return h->at<T>(off); }
+
+    louvain_status memset_ctl_range(size_t off, size_t bytes) {
+        HIPCHK(h, hipMemsetAsync((char*)ctl() + off, 0, bytes, s));
+        return LOUVAIN_OK;
+    }
+
+    // Upload per-bucket segment starts (host prefix of counts) to seg[base..].
+    louvain_status upload_seg(int base, const int64_t* segs, int count) {
+        int64_t* up = (int64_t*)h->pinned_up + base;
+        memcpy(up, segs, count * sizeof(int64_t));
+        HIPCHK(h, hipMemcpyAsync(at<int64_t>(h->lay.seg) + base, up, count * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, s));
+        return LOUVAIN_OK;
+    }
+
+    // Split the hub list into chunks whose table capacities fit the pool.
+    // Fails if one table alone exceeds the pool (cannot happen for
+    // capacities bounded by 2 * n, which the pool always holds).
+    bool chunks(const std::vector<int64_t>& pre, int64_t pool, std::vector<std::pair<int32_t, int32_t>>* out) {
+        out->clear();
+        const int32_t cnt = (int32_t)pre.size() - 1;
+        int32_t lo = 0;
+        while (lo < cnt) {
+            if (pre[lo + 1] - pre[lo] > pool) return false;
+            int32_t hi = lo + 1;
+            while (hi < cnt && pre[hi + 1] - pre[lo] <= pool) hi++;
+            out->push_back({lo, hi});
+            lo = hi;
+        }
+        return true;
+    }
+
+    louvain_status run();
+};
+
+louvain_status Runner::run() {
+    louvain_t* H = h;
+    const louvain_params& P = H->p;
+    const Layout& Y = H->lay;
+    const int64_t n0 = H->g.n;
+    const int64_t W = H->W;
+    const int sync = P.mode == LOUVAIN_SYNC;
+    const int prune = P.pruner == LOUVAIN_PRUNE_FLAGS;
+    int32_t* C = at<int32_t>(Y.C);
+    int32_t* Cp = at<int32_t>(Y.Cp);
+    i64* K = at<i64>(Y.K);
+    i64* Sig = at<i64>(Y.Sig);
+    uint32_t* mark = at<uint32_t>(Y.mark);
+    uint8_t* vb = at<uint8_t>(Y.vbucket);
+    int32_t* blist = at<int32_t>(Y.blist);
+    int32_t* qbuf[2] = {at<int32_t>(Y.qa), at<int32_t>(Y.qb)};
+    int64_t* seg = at<int64_t>(Y.seg);
+    void* scan = at<void>(Y.scan);
+
+    memset(&H->st, 0, sizeof(H->st));
+    H->recs.clear();
+    H->evnext = 0;
+    for (int k = 0; k < K_COUNT; k++) { H->kms[k] = 0; H->klaunch[k] = 0; H->kbytes[k] = 0; }
+    HIPCHK(H, hipMemsetAsync(ctl(), 0, sizeof(Ctl), s));
+    iota_i32(C, n0, s);
+
+    LevelView L = H->L0;
+    int cur_sup = 0;
+    bool stopped_before_aggregate = false;
+    bool have_newid = false;
+    int64_t ncom_last = 0;
+    std::vector<int32_t> hcp;
+    std::vector<int64_t> hsig;
+
+    for (int pass = 0; P.max_passes <= 0 || pass < P.max_passes; pass++) {
+        const int64_t n = L.n;
+        have_newid = false;
+        // ---------------- pass init: classify, bucket lists, K', Sigma'
+        HIPCHK(H, hipMemsetAsync(&ctl()->kmax, 0, sizeof(u64), s));
+        HIPCHK(H, hipMemsetAsync(ctl()->bcount, 0, 2 * MAX_BUCKETS * sizeof(int32_t), s));
+        int32_t bcount[MAX_BUCKETS];
+        timed(H, K_PASS_INIT, 0, [&] { launch_classify(L, H->mb, vb, Cp, K, Sig, ctl(), s); });
+        if ((st = readback(H, bcount, ctl()->bcount, sizeof(bcount))) != LOUVAIN_OK) return st;
+        const int NBT = NB_MOVE + 1;  // LDS buckets + hub
+        int64_t segs[MAX_BUCKETS + 1];
+        segs[0] = 0;
+        for (int b = 0; b < NBT; b++) segs[b + 1] = segs[b] + bcount[b];
+        const int64_t nonisolated = segs[NBT];
+        if ((st = upload_seg(0, segs, NBT + 1)) != LOUVAIN_OK) return st;
+        timed(H, K_PASS_INIT, 0, [&] {
+            launch_fill_buckets(n, vb, blist, seg, ctl(), s);
+            for (int b = 0; b < NBT; b++)
+                launch_rowsum(L, b, blist + segs[b], bcount[b], K, Sig, ctl(), s);
+        });
+        // hub tables
+        const int32_t nhub = bcount[NB_MOVE];
+        const int32_t* hub_list = blist + segs[NB_MOVE];
+        int64_t* hpre = at<int64_t>(Y.hpre);
+        std::vector<std::pair<int32_t, int32_t>> hub_chunks;
+        if (nhub > 0) {
+            launch_hub_caps(L, hub_list, nhub, at<int64_t>(Y.hcaps), s);
+            scan_i64_to_i64(at<int64_t>(Y.hcaps), hpre, nhub, scan, s);
+            hub_pre.resize(nhub + 1);
+            if ((st = readback(H, hub_pre.data(), hpre, (nhub + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
+            if (!chunks(hub_pre, Y.pool_entries, &hub_chunks))
+                return fail(H, LOUVAIN_ERR_WORKSPACE, "hub hash table exceeds the workspace pool");
+        }
+        u64 kmax = 0;
+        if ((st = readback(H, &kmax, &ctl()->kmax, sizeof(u64))) != LOUVAIN_OK) return st;
+        const bool wide = (unsigned __int128)(u64)W * kmax >= ((unsigned __int128)1 << 62);
+        LevelView LM = L;
+        LM.t.acc64 = kmax >= ((u64)1 << 32);
+
+        // ---------------- local moving
+        int32_t li = P.max_iterations;
+        int32_t counts[MAX_BUCKETS + 1];
+        for (int b = 0; b < NBT; b++) counts[b] = bcount[b];
+        const int32_t* cur_list = blist;  // iteration 0: every vertex with an arc
+        int qsel = 0;
+        u64 prev_b[5][MAX_BUCKETS] = {};
+        for (int t = 0; t < P.max_iterations; t++) {
+            const int pl = P.pick_less > 0 && ((t + P.pick_less / 2) % P.pick_less) == 0;
+            HIPCHK(H, hipMemsetAsync(ctl(), 0, offsetof(Ctl, err), s));
+            const uint32_t stamp_cur = H->stamp;
+            const uint32_t stamp_next = ++H->stamp;
+            int32_t* qnext = qbuf[qsel];
+            MoveArgs a{};
+            a.off = L.off;
+            a.idx = L.idx;
+            a.w = L.w;
+            a.Cp = Cp;
+            a.Sig = Sig;
+            a.K = K;
+            a.W = W;
+            a.wide = wide;
+            a.pl = pl;
+            a.prune = prune;
+            a.check_mark = (t > 0 && prune) ? 1 : 0;
+            a.stamp_cur = stamp_cur;
+            a.stamp_next = stamp_next;
+            a.mark = mark;
+            a.vbucket = vb;
+            a.qnext = qnext;
+            a.qseg = seg;
+            a.ctl = ctl();
+            a.movers = at<int32_t>(Y.movers);
+            a.hub_keys = at<int32_t>(Y.pool_keys);
+            a.hub_vals = at<void>(Y.pool_vals);
+            a.hub_off = hpre;
+            for (int b = 0; b < NB_MOVE; b++) {
+                if (counts[b] <= 0) continue;
+                a.bucket = b;
+                timed(H, K_MOVE0 + b, 0, [&] { launch_move(LM, b, sync, a, cur_list + segs[b], counts[b], s); });
+            }
+            // hubs: always walk the static hub list; unqueued hubs exit at once
+            if (nhub > 0 && (t == 0 || !prune || counts[NB_MOVE] > 0)) {
+                a.bucket = NB_MOVE;
+                for (auto& ch : hub_chunks) {
+                    a.hub_off = hpre + ch.first;
+                    a.hub_base = hub_pre[ch.first];
+                    timed(H, K_MOVE_HUB, 0,
+                          [&] { launch_move_hub(LM, sync, a, hub_list + ch.first, ch.second - ch.first, s); });
+                }
+                a.hub_off = hpre;
+            }
+            if (sync) timed(H, K_SYNC_APPLY, 0, [&] { launch_sync_apply(L, a, s); });
+            // read back the iteration's totals and per-bucket counters
+            struct {
+                IterRead it;
+            } rb;
+            if ((st = readback(H, &rb.it, ctl(), sizeof(IterRead))) != LOUVAIN_OK) return st;
+            u64 bc[5][MAX_BUCKETS];
+            if ((st = readback(H, bc, ctl()->b_eval, sizeof(bc))) != LOUVAIN_OK) return st;
+            const unsigned __int128 S = ((unsigned __int128)rb.it.s_hi << 64) | rb.it.s_lo;
+            H->st.iterations++;
+            H->st.moves += (int64_t)rb.it.moves;
+            // algorithmic bytes of this iteration's move launches, per bucket
+            if (H->prof) {
+                for (int b = 0; b < NBT; b++) {
+                    const u64 de = bc[0][b] - prev_b[0][b], da = bc[1][b] - prev_b[1][b],
+                              dd = bc[2][b] - prev_b[2][b], dm = bc[3][b] - prev_b[3][b],
+                              dma = bc[4][b] - prev_b[4][b];
+                    if (!de) continue;
+                    const int64_t bytes = move_alg_bytes(LM, de, da, dd, dm, dma, sync);
+                    const int kind = b < NB_MOVE ? K_MOVE0 + b : K_MOVE_HUB;
+                    for (auto it = H->recs.rbegin(); it != H->recs.rend(); ++it)
+                        if (it->kind == kind) { it->bytes += bytes; break; }
+                }
+            }
+            memcpy(prev_b, bc, sizeof(bc));
+            if (H->itfn) {
+                hcp.resize(n);
+                hsig.resize(n);
+                if ((st = readback(H, hcp.data(), Cp, n * 4)) != LOUVAIN_OK) return st;
+                if ((st = readback(H, hsig.data(), Sig, n * 8)) != LOUVAIN_OK) return st;
+                H->itfn(H->user, pass, t, n, hcp.data(), hsig.data(), (int64_t)rb.it.moves, (int64_t)rb.it.s_hi,
+                        rb.it.s_lo);
+            }
+            if (converged(S, W, P, pass)) { li = t + 1; break; }
+            // next iteration's queue
+            if (prune) {
+                int64_t total = 0;
+                for (int b = 0; b < NBT; b++) { counts[b] = rb.it.qcount[b]; total += counts[b]; }
+                cur_list = qnext;
+                qsel ^= 1;
+                if (total == 0) {
+                    // nothing flagged: the next iteration has S = 0 and converges
+                    if (t + 1 >= P.max_iterations) { li = P.max_iterations; break; }
+                    H->st.iterations++;
+                    if (H->itfn) {
+                        H->itfn(H->user, pass, t + 1, n, hcp.data(), hsig.data(), 0, 0, 0);
+                    }
+                    li = t + 2;
+                    break;
+                }
+            }
+        }
+        H->st.passes++;
+        if (pass < 32) H->st.iterations_per_pass[pass] = li;
+        stopped_before_aggregate = true;
+        if (li <= 1) break;
+
+        // ---------------- community counts and shrink tests
+        int32_t* used = at<int32_t>(Y.used);
+        int32_t* newid = at<int32_t>(Y.newid);
+        HIPCHK(H, hipMemsetAsync(used, 0, (n + 1) * 4, s));
+        timed(H, K_AGG_PREP, 0, [&] {
+            launch_mark_used(Cp, n, used, s);
+            scan_i32_to_i32(used, newid, n, scan, s);
+        });
+        int32_t gall = 0;
+        if ((st = readback(H, &gall, newid + n, 4)) != LOUVAIN_OK) return st;
+        have_newid = true;
+        ncom_last = gall;
+        const int64_t isolated = n - nonisolated;
+        const int64_t gamma = gall - isolated, gamma_old = nonisolated;
+        if (pass < 32) H->st.communities_per_pass[pass] = gall;
+        if (gamma == gamma_old) break;
+        if ((unsigned __int128)gamma * (unsigned __int128)P.agg_den >
+            (unsigned __int128)P.agg_num * (unsigned __int128)gamma_old)
+            break;
+
+        // ---------------- renumber, dendrogram lookup, community CSR
+        const int64_t ncom = gall;
+        int32_t* cnt = at<int32_t>(Y.cnt);
+        int32_t* coff = at<int32_t>(Y.coff);
+        int32_t* cursor = at<int32_t>(Y.cursor);
+        int32_t* members = at<int32_t>(Y.members);
+        int64_t* cdeg = at<int64_t>(Y.cdeg);
+        int64_t* hoff = at<int64_t>(Y.hoff);
+        HIPCHK(H, hipMemsetAsync(cnt, 0, (ncom + 1) * 4, s));
+        HIPCHK(H, hipMemsetAsync(cursor, 0, (ncom + 1) * 4, s));
+        HIPCHK(H, hipMemsetAsync(cdeg, 0, (ncom + 1) * 8, s));
+        HIPCHK(H, hipMemsetAsync(ctl()->bcount, 0, 2 * MAX_BUCKETS * sizeof(int32_t), s));
+        timed(H, K_AGG_PREP, 0, [&] {
+            launch_relabel(Cp, n, newid, s);
+            launch_dendrogram(C, n0, Cp, s);
+            launch_comm_count(L, Cp, cnt, cdeg, s);
+            scan_i32_to_i32(cnt, coff, ncom, scan, s);
+            scan_i64_to_i64(cdeg, hoff, ncom, scan, s);
+            launch_comm_fill(n, Cp, coff, cursor, members, s);
+            launch_agg_classify(ncom, hoff, ncom, H->ab, at<uint8_t>(Y.cbucket), at<int32_t>(Y.rowlen), ctl(), s);
+        });
+        int32_t acount[MAX_BUCKETS];
+        if ((st = readback(H, acount, ctl()->bcount, sizeof(acount))) != LOUVAIN_OK) return st;
+        const int NBA = NB_AGG + 1;
+        int64_t asegs[MAX_BUCKETS + 1];
+        asegs[0] = 0;
+        for (int b = 0; b < NBA; b++) asegs[b + 1] = asegs[b] + acount[b];
+        if ((st = upload_seg(16, asegs, NBA + 1)) != LOUVAIN_OK) return st;
+        int32_t* alist = at<int32_t>(Y.alist);
+        timed(H, K_AGG_PREP, 0,
+              [&] { launch_agg_fill(ncom, at<uint8_t>(Y.cbucket), alist, seg + 16, ctl(), s); });
+
+        // ---------------- super-row hashing into the holey buffer
+        const int nxt = cur_sup ^ 1;
+        AggArgs A{};
+        A.Cp = Cp;
+        A.coff = coff;
+        A.members = members;
+        A.hoff = hoff;
+        A.hidx = at<int32_t>(Y.hidx);
+        A.hw = at<void>(Y.hw);
+        A.rowlen = at<int32_t>(Y.rowlen);
+        A.out_w64 = H->sup_wk == 2;
+        A.hub_keys = at<int32_t>(Y.pool_keys);
+        A.hub_vals = at<void>(Y.pool_vals);
+        LevelView LA = L;
+        LA.t.acc64 = (u64)W >= ((u64)1 << 32);
+        for (int b = 0; b < NB_AGG; b++) {
+            if (acount[b] <= 0) continue;
+            timed(H, K_AGG0 + b, 0, [&] { launch_aggregate(LA, b, A, alist + asegs[b], acount[b], s); });
+        }
+        const int32_t nah = acount[NB_AGG];
+        if (nah > 0) {
+            const int32_t* ah_list = alist + asegs[NB_AGG];
+            launch_agg_caps(ah_list, nah, hoff, ncom, at<int64_t>(Y.hcaps), s);
+            scan_i64_to_i64(at<int64_t>(Y.hcaps), hpre, nah, scan, s);
+            hub_pre.resize(nah + 1);
+            if ((st = readback(H, hub_pre.data(), hpre, (nah + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
+            std::vector<std::pair<int32_t, int32_t>> ach;
+            if (!chunks(hub_pre, Y.pool_entries, &ach))
+                return fail(H, LOUVAIN_ERR_WORKSPACE, "community hash table exceeds the workspace pool");
+            for (auto& ch : ach) {
+                A.hub_off = hpre + ch.first;
+                A.hub_base = hub_pre[ch.first];
+                timed(H, K_AGG_HUB, 0,
+                      [&] { launch_aggregate_hub(LA, A, ah_list + ch.first, ch.second - ch.first, s); });
+            }
+        }
+        // ---------------- compaction into the next super-graph
+        void* goff = at<void>(Y.sup_off[nxt]);
+        int32_t* gidx = at<int32_t>(Y.sup_idx[nxt]);
+        void* gw = at<void>(Y.sup_w[nxt]);
+        launch_rowlen_to_offsets(at<int32_t>(Y.rowlen), ncom, goff, H->sup_off64, scan, s);
+        int64_t nnz2 = 0;
+        if (H->sup_off64) {
+            if ((st = readback(H, &nnz2, (int64_t*)goff + ncom, 8)) != LOUVAIN_OK) return st;
+        } else {
+            int32_t x = 0;
+            if ((st = readback(H, &x, (int32_t*)goff + ncom, 4)) != LOUVAIN_OK) return st;
+            nnz2 = x;
+        }
+        timed(H, K_COMPACT, 0, [&] {
+            launch_compact(ncom, hoff, A.hidx, A.hw, goff, H->sup_off64, gidx, gw, A.out_w64, s);
+        });
+        L.n = ncom;
+        L.nnz = nnz2;
+        L.off = goff;
+        L.idx = gidx;
+        L.w = gw;
+        L.t.off64 = H->sup_off64;
+        L.t.wk = H->sup_wk;
+        L.t.acc64 = 0;
+        cur_sup = nxt;
+        stopped_before_aggregate = false;
+        have_newid = false;
+        if (H->pafn) {
+            std::vector<int64_t> o(ncom + 1);
+            std::vector<int32_t> ii(nnz2);
+            std::vector<int64_t> ww(nnz2);
+            if (H->sup_off64) {
+                if ((st = readback(H, o.data(), goff, (ncom + 1) * 8)) != LOUVAIN_OK) return st;
+            } else {
+                std::vector<int32_t> o32(ncom + 1);
+                if ((st = readback(H, o32.data(), goff, (ncom + 1) * 4)) != LOUVAIN_OK) return st;
+                for (int64_t k = 0; k <= ncom; k++) o[k] = o32[k];
+            }
+            if ((st = readback(H, ii.data(), gidx, nnz2 * 4)) != LOUVAIN_OK) return st;
+            if (H->sup_wk == 2) {
+                if ((st = readback(H, ww.data(), gw, nnz2 * 8)) != LOUVAIN_OK) return st;
+            } else {
+                std::vector<int32_t> w32(nnz2);
+                if ((st = readback(H, w32.data(), gw, nnz2 * 4)) != LOUVAIN_OK) return st;
+                for (int64_t k = 0; k < nnz2; k++) ww[k] = w32[k];
+            }
+            H->pafn(H->user, pass, ncom, o.data(), ii.data(), ww.data(), li);
+        }
+    }
+
+    // ---------------- final lookup and dense renumbering
+    if (stopped_before_aggregate) {
+        const int64_t n = L.n;
+        int32_t* used = at<int32_t>(Y.used);
+        int32_t* newid = at<int32_t>(Y.newid);
+        if (!have_newid) {
+            HIPCHK(H, hipMemsetAsync(used, 0, (n + 1) * 4, s));
+            launch_mark_used(Cp, n, used, s);
+            scan_i32_to_i32(used, newid, n, scan, s);
+            int32_t gall = 0;
+            if ((st = readback(H, &gall, newid + n, 4)) != LOUVAIN_OK) return st;
+            ncom_last = gall;
+        }
+        launch_final_lookup(C, n0, Cp, newid, s);
+        H->ncom = ncom_last;
+    } else {
+        H->ncom = L.n;
+    }
+    HIPCHK(H, hipStreamSynchronize(s));
+    H->st.communities = H->ncom;
+    return LOUVAIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+louvain_status louvain_run(louvain_t* h) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    HIPCHK(h, hipEventRecord(e0, h->stream));
+    Runner r(h);
+    louvain_status st = r.run();
+    hipEventRecord(e1, h->stream);
+    hipEventSynchronize(e1);
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != LOUVAIN_OK) { h->ran = false; return st; }
+    h->st.ms_total = ms;
+    // per-kernel timing
+    if (h->prof) {
+        for (auto& r2 : h->recs) {
+            float km = 0;
+            if (hipEventElapsedTime(&km, r2.e0, r2.e1) == hipSuccess) h->kms[r2.kind] += km;
+            h->klaunch[r2.kind]++;
+            h->kbytes[r2.kind] += r2.bytes;
+        }
+        double mv = 0, ag = 0;
+        for (int k = K_MOVE0; k <= K_SYNC_APPLY; k++) mv += h->kms[k];
+        for (int k = K_AGG_PREP; k <= K_COMPACT; k++) ag += h->kms[k];
+        h->st.ms_move = mv;
+        h->st.ms_aggregate = ag;
+    }
+    Ctl c;
+    if (readback(h, &c, h->ctl(), sizeof(Ctl)) == LOUVAIN_OK) {
+        for (int b = 0; b < MAX_BUCKETS; b++) {
+            h->st.vertices_evaluated += (int64_t)c.b_eval[b];
+            h->st.arcs_scanned += (int64_t)c.b_arcs[b];
+            h->st.distinct_scanned += (int64_t)c.b_distinct[b];
+        }
+    }
+    h->ran = true;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_get_membership(louvain_t* h, int32_t* out) {
+    if (!h || !out) return fail(h, LOUVAIN_ERR_INVALID, "null argument");
+    if (!h->ran) return fail(h, LOUVAIN_ERR_STATE, "louvain_run has not completed");
+    if (h->g.n == 0) return LOUVAIN_OK;
+    HIPCHK(h, hipMemcpyAsync(out, h->at<int32_t>(h->lay.C), h->g.n * 4, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_modularity(louvain_t* h, double* q, int64_t num[2], int64_t den[2]) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    if (!h->ran) return fail(h, LOUVAIN_ERR_STATE, "louvain_run has not completed");
+    const int64_t n = h->g.n;
+    i64* sigin = h->at<i64>(h->lay.K);
+    i64* sigtot = h->at<i64>(h->lay.Sig);
+    if (n > 0) {
+        HIPCHK(h, hipMemsetAsync(sigin, 0, n * 8, h->stream));
+        HIPCHK(h, hipMemsetAsync(sigtot, 0, n * 8, h->stream));
+    }
+    HIPCHK(h, hipMemsetAsync(&h->ctl()->q_lo, 0, 16, h->stream));
+    launch_modularity(h->L0, h->at<int32_t>(h->lay.C), h->ncom, h->W, sigin, sigtot, h->ctl(), h->stream);
+    u64 qq[2];
+    louvain_status st = readback(h, qq, &h->ctl()->q_lo, 16);
+    if (st != LOUVAIN_OK) return st;
+    __int128 numv = (__int128)(((unsigned __int128)qq[1] << 64) | qq[0]);
+    __int128 denv = h->W == 0 ? (__int128)1 : (__int128)h->W * h->W;
+    if (h->W == 0) numv = 0;
+    if (num) { num[0] = (int64_t)(numv >> 64); num[1] = (int64_t)(uint64_t)numv; }
+    if (den) { den[0] = (int64_t)(denv >> 64); den[1] = (int64_t)(uint64_t)denv; }
+    if (q) *q = (double)numv / (double)denv;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_get_stats(louvain_t* h, louvain_stats* s) {
+    if (!h || !s) return fail(h, LOUVAIN_ERR_INVALID, "null argument");
+    *s = h->st;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_set_profiling(louvain_t* h, int32_t enable) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    h->prof = enable != 0;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_get_kernel_stats(louvain_t* h, louvain_kernel_stat* out, int32_t max, int32_t* count) {
+    if (!h || !count || (max > 0 && !out)) return fail(h, LOUVAIN_ERR_INVALID, "null argument");
+    int32_t k = 0;
+    for (int i = 0; i < K_COUNT; i++) {
+        if (!h->klaunch[i]) continue;
+        if (k < max) {
+            memset(&out[k], 0, sizeof(out[k]));
+            snprintf(out[k].name, sizeof(out[k].name), "%s", KNAMES[i]);
+            out[k].launches = h->klaunch[i];
+            out[k].ms = h->kms[i];
+            out[k].alg_bytes = h->kbytes[i];
+        }
+        k++;
+    }
+    *count = k;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_set_trace(louvain_t* h, louvain_iter_fn iter_fn, louvain_pass_fn pass_fn, void* user) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    h->itfn = iter_fn;
+    h->pafn = pass_fn;
+    h->user = user;
+    return LOUVAIN_OK;
+}
+
+const char* louvain_last_error(const louvain_t* h) {
+    if (!h) return g_create_error.c_str();
+    return h->err.c_str();
+}
+
+void louvain_destroy(louvain_t* h) {
+    if (!h) return;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    else hipDeviceSynchronize();
+    for (auto e : h->evpool) hipEventDestroy(e);
+    if (h->pinned) hipHostFree(h->pinned);
+    if (h->pinned_up) hipHostFree(h->pinned_up);
+    delete h;
+}
+
+}  // extern "C"

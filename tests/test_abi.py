@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/louvain.h declares, and rejects bad arguments before touching a
+GPU.  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2501_19004_amd as lv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "louvain.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(louvain_[a-z_]+)\s*\(", text)) - {"louvain_iter_fn", "louvain_pass_fn"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lv.LIB_PATH):
+        pytest.skip("library not built")
+    return lv.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(lv.EXPORTED) == syms
+
+
+def test_params_default_are_the_papers(lib):
+    p = lv.louvain_params_default()
+    assert (p.max_iterations, p.max_passes, p.tol_num, p.tol_den, p.tol_drop) == (20, 10, 1, 100, 10)
+    assert (p.agg_num, p.agg_den, p.pick_less, p.mode, p.pruner) == (4, 5, 4, lv.ASYNC, lv.PRUNE_FLAGS)
+
+
+def test_struct_sizes_match_header(lib):
+    # louvain_graph: 2 int64 + int32 (+pad) + 3 pointers
+    assert ctypes.sizeof(lv.LouvainGraph) == 48
+    assert ctypes.sizeof(lv.LouvainParams) == 4 * 2 + 8 * 5 + 4 * 4 + 4 * 24
+    assert ctypes.sizeof(lv.LouvainKernelStat) == 48 + 8 * 3
+
+
+def test_workspace_size_is_host_only_and_monotone(lib):
+    p = lv.louvain_params_default()
+    sizes = []
+    for n, m in [(0, 0), (10, 20), (1000, 20000), (1 << 20, 1 << 24)]:
+        g = lv.LouvainGraph(n, m, 32, None, None, None)
+        sizes.append(lv.louvain_workspace_size(g, p))
+    assert sizes == sorted(sizes) and sizes[0] > 0
+
+
+@pytest.mark.parametrize("field,value", [("n", -1), ("nnz", -5), ("n", 1 << 31)])
+def test_workspace_size_rejects_bad_sizes(lib, field, value):
+    g = lv.LouvainGraph(10, 20, 32, None, None, None)
+    setattr(g, field, value)
+    with pytest.raises(lv.LouvainError) as e:
+        lv.louvain_workspace_size(g, lv.louvain_params_default())
+    assert e.value.status == lv.LOUVAIN_ERR_INVALID
+
+
+def _create_status(g, p, ws=None, ws_bytes=0):
+    h = ctypes.c_void_p()
+    st = lib_handle().louvain_create(ctypes.byref(g), ctypes.byref(p), None, ws, ws_bytes, ctypes.byref(h))
+    return st, h
+
+
+def lib_handle():
+    return lv.load_library()
+
+
+def test_create_rejects_bad_arguments_before_device_access(lib):
+    p = lv.louvain_params_default()
+    fake = 4096  # never dereferenced: every case fails argument checks first
+    g = lv.LouvainGraph(10, 20, 16, fake, fake, None)
+    assert _create_status(g, p)[0] == lv.LOUVAIN_ERR_INVALID           # offset_bits
+    g = lv.LouvainGraph(10, 1 << 31, 32, fake, fake, None)
+    assert _create_status(g, p)[0] == lv.LOUVAIN_ERR_INVALID           # nnz too big for 32-bit offsets
+    g = lv.LouvainGraph(10, 20, 32, None, fake, None)
+    assert _create_status(g, p)[0] == lv.LOUVAIN_ERR_INVALID           # missing offsets
+    g = lv.LouvainGraph(10, 20, 32, fake, fake, None)
+    bad = lv.louvain_params_default()
+    bad.tol_den = 0
+    assert _create_status(g, bad)[0] == lv.LOUVAIN_ERR_INVALID         # tolerance denominator
+    bad = lv.louvain_params_default()
+    bad.mode = 7
+    assert _create_status(g, bad)[0] == lv.LOUVAIN_ERR_INVALID
+    assert _create_status(g, p, None, 0)[0] == lv.LOUVAIN_ERR_WORKSPACE  # no workspace
+    assert _create_status(g, p, fake + 8, 1 << 40)[0] == lv.LOUVAIN_ERR_WORKSPACE  # misaligned
+    assert "256-byte" in lv.louvain_last_error(None)
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.louvain_run(None) == lv.LOUVAIN_ERR_INVALID
+    assert lib.louvain_get_membership(None, None) == lv.LOUVAIN_ERR_INVALID
+    lib.louvain_destroy(None)

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+SYNC mode must match the oracle bit for bit: memberships C' and community
+totals Sigma' after every local-moving iteration, the moves and exact gain
+sum of each iteration, every super-graph (row-sorted CSR), the final
+membership and the exact modularity.  ASYNC mode must reach modularity within
+0.002 of the sequential oracle.  Degree buckets are forced through every
+code path (LDS groups of each width, workgroup tables, global hub tables).
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lv = pytest.importorskip("paper_2501_19004_amd")
+
+ALL_HUB = dict(bucket_max_degree=[-1] * 5, agg_bucket_max=[-1] * 4)
+ONLY_WG = dict(bucket_max_degree=[-1, -1, -1, -1, 4096], agg_bucket_max=[-1, -1, -1, 4096])
+SMALL_B = dict(bucket_max_degree=[2, 8, 16, 64, 128], agg_bucket_max=[4, 16, 64, 256])
+CONFIGS = {"default": {}, "all_hub": ALL_HUB, "only_wg": ONLY_WG, "small_buckets": SMALL_B}
+
+
+def star_plus_cliques(leaves=9000, cliques=30, k=6):
+    edges = [(0, 1 + i, 1) for i in range(leaves)]
+    base = leaves + 1
+    for c in range(cliques):
+        for x in range(k):
+            for y in range(x + 1, k):
+                edges.append((base + c * k + x, base + c * k + y, 2))
+        edges.append((base + c * k, 1 + c, 1))
+    return gg.from_edges(base + cliques * k, edges, "star+cliques")
+
+
+GRAPHS = {
+    "planted": lambda: gg.planted_partition(seed=1),
+    "ring10x5": lambda: gg.ring_of_cliques(10, 5),
+    "small_loops": lambda: gg.random_small(60, 0.12, 3, wmax=5, self_loops=True),
+    "rmat10": lambda: gg.rmat(10, 8, seed=3),
+    "rmat12w": lambda: gg.rmat(12, 16, seed=4, wmax=7),
+    "grid48": lambda: gg.grid(48, 48, seed=5),
+    "sbm": lambda: gg.sbm_degree(6000, 24, 14.0, seed=6, wmin=1, wmax=4),
+    "star": star_plus_cliques,
+    "k2": lambda: gg.from_edges(2, [(0, 1, 1)]),
+}
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+def run_gpu(g, mode, trace=True, **kw):
+    off, idx, w = lv.graph_tensors(g, dev())
+    L = lv.Louvain(off, idx, w, mode=mode, **kw)
+    iters, graphs = [], []
+    if trace:
+        L.trace(lambda p, t, cp, sig, m, gain: iters.append((p, t, cp, sig, m, gain)),
+                lambda p, n, o, i, ww, it: graphs.append((n, o, i, ww)))
+    L.run()
+    memb = L.membership().cpu().numpy()
+    q = L.modularity()
+    st = L.stats()
+    L.close()
+    return memb, q, iters, graphs, st
+
+
+def oracle_params(kw, mode):
+    p = oracle.Params(mode=mode)
+    for k, v in kw.items():
+        if k in ("max_iterations", "max_passes", "tol_num", "tol_den", "tol_drop", "agg_num", "agg_den"):
+            setattr(p, k, v)
+        if k == "pick_less":
+            p.pick_less = v
+        if k == "pruner":
+            p.prune = v
+    return p
+
+
+def assert_sync_equal(g, kw):
+    memb, (q, num, den), iters, graphs, st = run_gpu(g, lv.SYNC, **kw)
+    ref = oracle.louvain(g, oracle_params(kw, oracle.SYNC), trace=True)
+    assert len(iters) == len(ref.iters)
+    for a, b in zip(iters, ref.iters):
+        where = f"pass {b['pass_']} iter {b['iter']}"
+        assert (a[0], a[1]) == (b["pass_"], b["iter"]), where
+        assert np.array_equal(a[2], b["cprime"]), where
+        assert np.array_equal(a[3], b["sigma"]), where
+        assert (a[4], a[5]) == (b["moves"], b["gain"]), where
+    assert len(graphs) == len(ref.graphs)
+    for a, b in zip(graphs, ref.graphs):
+        assert a[0] == b["n"]
+        assert np.array_equal(a[1], b["offsets"])
+        assert np.array_equal(a[2], b["indices"])
+        assert np.array_equal(a[3], b["weights"])
+    assert np.array_equal(memb, ref.membership)
+    assert (num, den) == oracle.modularity_parts(g, memb)
+    assert st.communities == ref.communities and st.passes == ref.passes and st.iterations == ref.iterations
+
+
+@pytest.mark.parametrize("cfg", list(CONFIGS))
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_sync_bit_exact(name, cfg):
+    assert_sync_equal(GRAPHS[name](), CONFIGS[cfg])
+
+
+@pytest.mark.parametrize("name", ["planted", "rmat10", "grid48", "small_loops"])
+def test_sync_bit_exact_without_pruning(name):
+    assert_sync_equal(GRAPHS[name](), dict(pruner=lv.PRUNE_NONE))
+
+
+@pytest.mark.parametrize("kw", [dict(max_passes=0, agg_num=1, agg_den=1), dict(tol_num=0, tol_den=1),
+                                dict(pick_less=0, max_iterations=7), dict(pick_less=2, tol_drop=1)],
+                         ids=["to_convergence", "zero_tol", "no_pl", "pl2"])
+def test_sync_bit_exact_parameters(kw):
+    assert_sync_equal(gg.planted_partition(seed=2), kw)
+
+
+def test_sync_deterministic_across_runs():
+    g = gg.rmat(12, 16, seed=9)
+    a = run_gpu(g, lv.SYNC, trace=False)
+    b = run_gpu(g, lv.SYNC, trace=False)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+@pytest.mark.parametrize("g", [gg.from_edges(1, []), gg.from_edges(6, []), gg.from_edges(4, [(1, 1, 3), (2, 2, 1)]),
+                               gg.from_edges(7, [(0, 1, 1), (1, 2, 1), (0, 2, 1), (4, 5, 2)])],
+                         ids=["one_vertex", "no_edges", "self_loops_only", "isolated_mix"])
+@pytest.mark.parametrize("mode", [lv.SYNC, lv.ASYNC])
+def test_edge_cases(g, mode):
+    memb, (q, num, den), _, _, st = run_gpu(g, mode)
+    ref = oracle.louvain(g, oracle.Params(mode=mode))
+    if mode == lv.SYNC:
+        assert np.array_equal(memb, ref.membership)
+    assert sorted(set(memb.tolist())) == list(range(st.communities))
+    assert (num, den) == oracle.modularity_parts(g, memb)
+
+
+def test_empty_graph():
+    off = torch.zeros(1, dtype=torch.int32, device=dev())
+    idx = torch.zeros(0, dtype=torch.int32, device=dev())
+    L = lv.Louvain(off, idx, None)
+    L.run()
+    assert L.membership().numel() == 0
+    q, num, den = L.modularity()
+    assert (q, num, den) == (0.0, 0, 1)
+    L.close()
+
+
+@pytest.mark.parametrize("name,seed", [("planted", 1), ("planted", 2), ("planted", 3)])
+def test_async_quality_planted(name, seed):
+    g = gg.planted_partition(seed=seed)
+    memb, (q, num, den), _, _, _ = run_gpu(g, lv.ASYNC, trace=False)
+    qo = oracle.modularity(g, oracle.louvain(g).membership)
+    assert (num, den) == oracle.modularity_parts(g, memb)
+    assert abs(q - qo) <= 0.002, (q, qo)
+
+
+@pytest.mark.parametrize("make", [lambda: gg.rmat(14, 16, seed=5), lambda: gg.grid(128, 128, seed=6),
+                                  lambda: gg.sbm_degree(20000, 32, 16.0, seed=7, wmin=1, wmax=4),
+                                  lambda: gg.rmat(12, 8, seed=8, wmax=9)],
+                         ids=["rmat14", "grid128", "sbm20k", "rmat12w"])
+def test_async_quality(make):
+    g = make()
+    memb, (q, num, den), _, _, _ = run_gpu(g, lv.ASYNC, trace=False)
+    qo = oracle.modularity(g, oracle.louvain(g).membership)
+    assert (num, den) == oracle.modularity_parts(g, memb)
+    assert sorted(set(memb.tolist())) == list(range(int(memb.max()) + 1))
+    assert abs(q - qo) <= 0.002, (q, qo)
+
+
+def test_invalid_graph_rejected():
+    g = gg.ring_of_cliques(4, 4)
+    off, idx, w = lv.graph_tensors(g, dev())
+    bad = idx.clone()
+    bad[3] = g.n + 5
+    with pytest.raises(lv.LouvainError) as e:
+        lv.Louvain(off, bad, w)
+    assert e.value.status == lv.LOUVAIN_ERR_INVALID
+    wneg = torch.ones(idx.numel(), dtype=torch.int32, device=dev())
+    wneg[0] = 0
+    with pytest.raises(lv.LouvainError):
+        lv.Louvain(off, idx, wneg)

@@ -434,3 +434,32 @@ def test_async_pruning_order(g):
                 nbrs = {int(j) for j in lvl.indices[lvl.offsets[v]:lvl.offsets[v + 1]] if j != v}
                 assert any((j in prev_movers and j > v) or (j in movers and j < v) for j in nbrs), v
         prev_c, prev_movers, prev_pass = rec["cprime"], movers, rec["pass_"]
+
+
+@pytest.mark.parametrize("g", [gg.planted_partition(seed=1), gg.random_small(30, 0.2, 6, wmax=4, self_loops=True)],
+                         ids=lambda g: g.name)
+def test_sync_without_pruning_matches_single_vertex_sweeps(g):
+    """SYNC without pruning: every vertex decides against the iteration's
+    start state.  Rebuild each iteration from the single-vertex decision
+    routine (a separate sparse implementation) and compare."""
+    W = g.total_weight
+    w = g.weights.astype(np.int64)
+    K = np.zeros(g.n, dtype=np.int64)
+    np.add.at(K, np.repeat(np.arange(g.n), np.diff(g.offsets)), w)
+    C = np.arange(g.n, dtype=np.int32)
+    S = K.copy()
+    r = oracle.louvain(g, oracle.Params(mode=oracle.SYNC, prune=0), trace=True)
+    for rec in [x for x in r.iters if x["pass_"] == 0][:8]:
+        t = rec["iter"]
+        pl = (t + 2) % 4 == 0
+        dec = C.copy()
+        for i in range(g.n):
+            d, gain = oracle.best_move(g, W, C, S, i)
+            if d is None or gain <= 0 or (pl and d > C[i]):
+                continue
+            dec[i] = d
+        for i in np.flatnonzero(dec != C):
+            S[C[i]] -= K[i]
+            S[dec[i]] += K[i]
+        C = dec
+        assert np.array_equal(C, rec["cprime"]) and np.array_equal(S, rec["sigma"])
