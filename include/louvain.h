@@ -92,7 +92,23 @@ typedef struct {
      * bucket use global-memory hash tables.  Used by tests to force paths. */
     int32_t bucket_max_degree[8];
     int32_t agg_bucket_max[8];
-    int32_t reserved[8];
+    /* ASYNC only: 1 (default) makes reads and writes of C' and Sigma' in the
+     * local-moving kernels device-coherent, so a workgroup sees moves made by
+     * workgroups on other chiplets within the same launch; 0 uses cached
+     * loads (moves become visible at kernel boundaries). */
+    int32_t async_coherent;
+    /* Order in which degree buckets are launched within an iteration:
+     * 0 = low degree first (default), 1 = high degree first. */
+    int32_t bucket_order;
+    /* ASYNC only: split every iteration into this many sequential launches
+     * over consecutive slices of each bucket's queue (sorted by vertex id);
+     * later slices see the moves of earlier ones.  1 = one launch per bucket;
+     * default 64. */
+    int32_t async_slices;
+    /* ASYNC only: apply async_slices to the first this-many iterations of
+     * every pass (0 = to every iteration). */
+    int32_t async_slice_iters;
+    int32_t reserved[4];
 } louvain_params;
 
 /* Per-run counters, filled by louvain_get_stats after louvain_run. */

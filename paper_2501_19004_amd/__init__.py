@@ -42,7 +42,9 @@ class LouvainParams(ctypes.Structure):
                 ("agg_num", ctypes.c_int64), ("agg_den", ctypes.c_int64), ("pick_less", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("pruner", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("bucket_max_degree", ctypes.c_int32 * 8), ("agg_bucket_max", ctypes.c_int32 * 8),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("async_coherent", ctypes.c_int32), ("bucket_order", ctypes.c_int32),
+                ("async_slices", ctypes.c_int32), ("async_slice_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class LouvainStats(ctypes.Structure):

@@ -9,10 +9,12 @@
 //   community total degree + scan -> "holey" row bounds;
 //   per community: hash (d, w) in an LDS table, bitonic-sort the table in
 //   LDS, write the sorted distinct entries into the holey row;
-//   large communities: a global-memory table, sorted in place;
+//   big communities: many workgroups per community, LDS pre-aggregation
+//   into a global table, sorted extraction through a key bitmap;
 //   scan of distinct counts -> compacted, row-sorted super-graph CSR.
 #include <algorithm>
 
+#include "lv_bucket.h"
 #include "lv_internal.h"
 
 namespace lv {
@@ -43,18 +45,6 @@ void dispatch_types(const LevelTypes& t, Fn&& fn) {
 }
 
 inline unsigned blocks_for(int64_t items, int per_block) { return (unsigned)((items + per_block - 1) / per_block); }
-
-__device__ __forceinline__ void wave_count(bool want, int b, int32_t* count) {
-    const int lane = __lane_id();
-    u64 pending = __ballot(want);
-    while (pending) {
-        int leader = __ffsll((long long)pending) - 1;
-        int lb = __shfl(b, leader);
-        u64 same = __ballot(want && b == lb);
-        if (lane == leader) atomicAdd(&count[lb], __popcll(same));
-        pending &= ~same;
-    }
-}
 
 // Inclusive scan over a group of G lanes (G > 64: whole workgroup via LDS).
 template <int G>
@@ -199,41 +189,187 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_aggregate_lds(Graph<OffT,
     }
 }
 
-// Large communities: one 1024-thread workgroup, table in the global pool
-// (capacity >= 2 * bound, power of two), sorted in place after hashing.
+// ------------------------------------------------------------ big communities
+// A community whose distinct-neighbour bound exceeds the largest LDS bucket,
+// or whose arcs exceed BIG_ARCS, is spread over many workgroups.  Its arcs
+// are laid end to end in community-vertex order ("virtual arcs": virtual arc
+// f belongs to the member k with mpos[k] <= f < mpos[k+1], where mpos is the
+// exclusive prefix of member degrees; community c's virtual range starts at
+// hoff[c]).  Each chunk of BIG_CH virtual arcs is hashed into an LDS table,
+// then the table's distinct entries are added into the community's global
+// table.  Extraction marks the keys in a bitmap over [0, ncom) and walks it
+// in order, which yields the row sorted by neighbour id.
+
+// Exclusive-prefix input: degree of each member in community-vertex order.
+template <typename OffT>
+__global__ void k_member_deg(const OffT* __restrict__ off, const int32_t* __restrict__ members, int64_t n,
+                             int64_t* __restrict__ md) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t m = members[k];
+    md[k] = (int64_t)off[m + 1] - (int64_t)off[m];
+}
+
+__global__ void k_big_info(const int32_t* __restrict__ list, int32_t nbig, const int64_t* __restrict__ hoff,
+                           int64_t ncom, int64_t* __restrict__ nch, int64_t* __restrict__ cap) {
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= nbig) return;
+    const int32_t c = list[h];
+    const int64_t cdeg = hoff[c + 1] - hoff[c];
+    nch[h] = (cdeg + BIG_CH - 1) / BIG_CH;
+    const int64_t bound = cdeg < ncom ? cdeg : ncom;
+    uint64_t t = 1;
+    while (t < 2 * (uint64_t)bound) t <<= 1;
+    cap[h] = (int64_t)t;
+}
+
+__global__ void k_big_clear(int32_t* __restrict__ keys, u64* __restrict__ vals, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < count; s += stride) {
+        keys[s] = EMPTY_KEY;
+        vals[s] = 0;
+    }
+}
+
+// largest h in [0, n) with pre[h] - base <= x (pre non-decreasing, pre[0] - base <= x)
+__device__ __forceinline__ int32_t find_owner(const int64_t* pre, int32_t n, int64_t base, int64_t x) {
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] - base <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <typename OffT, int WK, typename AccT>
-__global__ void __launch_bounds__(1024) k_aggregate_hub(Graph<OffT, WK> g, AggArgs a,
-                                                        const int32_t* __restrict__ list, int32_t count) {
+__global__ void __launch_bounds__(1024) k_big_insert(Graph<OffT, WK> g, BigArgs a) {
     constexpr int G = 1024;
+    constexpr int L2C = Log2<BIG_LCAP>::v;
+    __shared__ int32_t s_keys[BIG_LCAP];
+    __shared__ AccT s_vals[BIG_LCAP];
     __shared__ i64 s_start[G], s_pre[G];
     __shared__ i64 s_t[G / WAVE];
-    const int64_t slot = blockIdx.x;
-    if (slot >= count) return;
-    const int32_t c = list[slot];
-    const int lane = threadIdx.x;
-    const int64_t toff = a.hub_off[slot] - a.hub_base;
-    const int64_t cap = a.hub_off[slot + 1] - a.hub_off[slot];
-    const int log2cap = __ffsll((long long)cap) - 1;
-    int32_t* keys = a.hub_keys + toff;
-    AccT* vals = (AccT*)a.hub_vals + toff;
-    for (int64_t s = lane; s < cap; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }
-    __syncthreads();
-    feed_members<OffT, WK, AccT, G>(g, a.Cp, a.members, a.coff[c], a.coff[c + 1], lane, s_start, s_pre, s_t,
-                                    [&](int32_t d, AccT w) {
-                                        table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap),
-                                                        d, w);
-                                    });
-    i64 L = 0;
-    for (int64_t s = lane; s < cap; s += G) L += keys[s] != EMPTY_KEY;
-    L = group_sum<G>(L, s_t);
-    bitonic_sort_group<G, AccT>(keys, vals, cap, lane);
-    const i64 h = a.hoff[c];
-    for (i64 x = lane; x < L; x += G) {
-        a.hidx[h + x] = keys[x];
-        if (a.out_w64) ((i64*)a.hw)[h + x] = (i64)vals[x];
-        else ((int32_t*)a.hw)[h + x] = (int32_t)vals[x];
+    __shared__ int64_t s_info[4];
+    const int tid = threadIdx.x;
+    const int64_t chunk = blockIdx.x;
+    for (int s = tid; s < BIG_LCAP; s += G) { s_keys[s] = EMPTY_KEY; s_vals[s] = 0; }
+    if (tid == 0) {
+        const int32_t h = find_owner(a.chunk_pre, a.nbig, a.chunk_base, chunk);
+        const int32_t c = a.list[h];
+        const int64_t f0 = a.hoff[c] + (chunk - (a.chunk_pre[h] - a.chunk_base)) * BIG_CH;
+        const int64_t f1 = min(f0 + (int64_t)BIG_CH, a.hoff[c + 1]);
+        // first member whose virtual range contains f0; first member starting at or after f1
+        int64_t lo = a.coff[c], hi = a.coff[c + 1] - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.mpos[mid] <= f0) lo = mid; else hi = mid - 1;
+        }
+        int64_t k1lo = lo, k1hi = a.coff[c + 1];
+        while (k1lo < k1hi) {
+            const int64_t mid = (k1lo + k1hi) >> 1;
+            if (a.mpos[mid] < f1) k1lo = mid + 1; else k1hi = mid;
+        }
+        s_info[0] = h;
+        s_info[1] = lo;
+        s_info[2] = k1lo;
+        s_info[3] = f0;
+        s_t[0] = f1;
     }
-    if (lane == 0) a.rowlen[c] = (int32_t)L;
+    __syncthreads();
+    const int32_t h = (int32_t)s_info[0];
+    const int64_t k0 = s_info[1], k1 = s_info[2], f0 = s_info[3];
+    const int64_t f1 = s_t[0];
+    __syncthreads();
+    for (int64_t kb = k0; kb < k1; kb += G) {
+        i64 start = 0, deg = 0;
+        if (kb + tid < k1) {
+            const int64_t k = kb + tid;
+            const int32_t m = a.members[k];
+            const int64_t v0 = max(a.mpos[k], f0), v1 = min(a.mpos[k + 1], f1);
+            start = (i64)g.off[m] + (v0 - a.mpos[k]);
+            deg = v1 > v0 ? v1 - v0 : 0;
+        }
+        const i64 pre = group_incl_scan<G>(deg, s_t);
+        s_start[tid] = start;
+        s_pre[tid] = pre;
+        __syncthreads();
+        const i64 total = s_pre[G - 1];
+        for (i64 f = tid; f < total; f += G) {
+            int lo = 0, hi = G - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pre[mid] > f) hi = mid; else lo = mid + 1;
+            }
+            const i64 e = s_start[lo] + (f - (lo ? s_pre[lo - 1] : 0));
+            const int32_t d = a.Cp[g.idx[e]];
+            table_add<AccT>(s_keys, s_vals, BIG_LCAP - 1, hash_slot<L2C>(d), d, (AccT)g.weight(e));
+        }
+        __syncthreads();
+    }
+    // merge the chunk's distinct entries into the community's global table
+    const int64_t toff = a.tab_pre[h] - a.tab_base;
+    const int64_t cap = a.tab_pre[h + 1] - a.tab_pre[h];
+    const int log2cap = __ffsll((long long)cap) - 1;
+    int32_t* keys = a.keys + toff;
+    AccT* vals = (AccT*)a.vals + toff;
+    for (int s = tid; s < BIG_LCAP; s += G) {
+        const int32_t d = s_keys[s];
+        if (d != EMPTY_KEY) table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d, s_vals[s]);
+    }
+}
+
+template <typename AccT>
+__device__ __forceinline__ AccT table_get(const int32_t* keys, const AccT* vals, uint32_t mask, uint32_t s,
+                                          int32_t key) {
+    for (uint32_t step = 1;; ++step) {
+        if (keys[s] == key) return vals[s];
+        s = (s + step) & mask;
+    }
+}
+
+template <typename AccT>
+__global__ void __launch_bounds__(1024) k_big_extract(BigArgs a) {
+    constexpr int G = 1024;
+    __shared__ i64 s_t[G / WAVE];
+    const int tid = threadIdx.x;
+    uint32_t* bm = a.bitmaps + (int64_t)blockIdx.x * a.words;
+    for (int32_t h = blockIdx.x; h < a.nbig; h += gridDim.x) {
+        const int32_t c = a.list[h];
+        const int64_t toff = a.tab_pre[h] - a.tab_base;
+        const int64_t cap = a.tab_pre[h + 1] - a.tab_pre[h];
+        const int log2cap = __ffsll((long long)cap) - 1;
+        const int32_t* keys = a.keys + toff;
+        const AccT* vals = (const AccT*)a.vals + toff;
+        for (int64_t w = tid; w < a.words; w += G) bm[w] = 0;
+        __syncthreads();
+        for (int64_t s = tid; s < cap; s += G) {
+            const int32_t d = keys[s];
+            if (d != EMPTY_KEY) atomicOr(&bm[d >> 5], 1u << (d & 31));
+        }
+        __syncthreads();
+        const int64_t per = (a.words + G - 1) / G;
+        const int64_t w0 = min((int64_t)tid * per, a.words), w1 = min(w0 + per, a.words);
+        i64 cnt = 0;
+        for (int64_t w = w0; w < w1; w++) cnt += __popc(bm[w]);
+        const i64 incl = group_incl_scan<G>(cnt, s_t);
+        i64 rank = incl - cnt;
+        const int64_t base = a.hoff[c];
+        for (int64_t w = w0; w < w1; w++) {
+            uint32_t bits = bm[w];
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int32_t d = (int32_t)(w * 32 + b);
+                const AccT v = table_get<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d);
+                a.hidx[base + rank] = d;
+                if (a.out_w64) ((i64*)a.hw)[base + rank] = (i64)v;
+                else ((int32_t*)a.hw)[base + rank] = (int32_t)v;
+                rank++;
+            }
+        }
+        if (tid == G - 1) a.rowlen[c] = (int32_t)incl;
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------ small kernels
@@ -271,40 +407,24 @@ __global__ void k_comm_fill(int64_t n, const int32_t* __restrict__ Cp, const int
     const int32_t c = Cp[v];
     members[coff[c] + atomicAdd(&cursor[c], 1)] = (int32_t)v;
 }
-__global__ void k_agg_classify(int64_t ncom, const int64_t* __restrict__ hoff, int64_t bound_cap, Buckets B,
-                               uint8_t* __restrict__ cbucket, int32_t* __restrict__ rowlen, Ctl* ctl) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int b = 255;
-    if (c < ncom) {
-        int64_t bound = hoff[c + 1] - hoff[c];
-        bound = bound < bound_cap ? bound : bound_cap;
-        if (bound > 0) {
-            b = B.nb;
+// Aggregation bucket of community c: by the bound min(total degree, ncom)
+// on its distinct neighbours; communities with more than BIG_ARCS arcs, or
+// a bound above every LDS bucket, take the big path (bucket nb); empty rows
+// (isolated members only) need no work.
+struct AggBucket {
+    const int64_t* hoff;
+    int64_t bound_cap;
+    Buckets B;
+    __device__ __forceinline__ int operator()(int64_t c) const {
+        const int64_t cdeg = hoff[c + 1] - hoff[c];
+        const int64_t bound = cdeg < bound_cap ? cdeg : bound_cap;
+        if (bound <= 0) return 255;
+        if (cdeg <= BIG_ARCS)
             for (int k = 0; k < B.nb; k++)
-                if (bound <= B.maxdeg[k]) { b = k; break; }
-        }
-        cbucket[c] = (uint8_t)b;
-        rowlen[c] = 0;
+                if (bound <= B.maxdeg[k]) return k;
+        return B.nb;
     }
-    wave_count(c < ncom && b != 255, b, ctl->bcount);
-}
-__global__ void k_agg_fill(int64_t ncom, const uint8_t* __restrict__ cbucket, int32_t* __restrict__ alist,
-                           const int64_t* __restrict__ seg, Ctl* ctl) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = c < ncom ? cbucket[c] : 255;
-    wave_enqueue(b != 255, b, (int32_t)c, alist, seg, ctl->bcursor);
-}
-__global__ void k_agg_caps(const int32_t* __restrict__ list, int32_t count, const int64_t* __restrict__ hoff,
-                           int64_t bound_cap, int64_t* __restrict__ caps) {
-    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= count) return;
-    const int32_t c = list[h];
-    int64_t bound = hoff[c + 1] - hoff[c];
-    bound = bound < bound_cap ? bound : bound_cap;
-    uint64_t cap = 1;
-    while (cap < 2 * (uint64_t)bound) cap <<= 1;
-    caps[h] = (int64_t)cap;
-}
+};
 
 // Copy each holey row to its compacted position; 32 lanes per row.
 template <typename GOffT>
@@ -412,17 +532,21 @@ void launch_comm_fill(int64_t n, const int32_t* Cp, const int32_t* coff, int32_t
                       hipStream_t s) {
     if (n > 0) k_comm_fill<<<blocks_for(n, 256), 256, 0, s>>>(n, Cp, coff, cursor, members);
 }
-void launch_agg_classify(int64_t ncom, const int64_t* hoff, int64_t bound_cap, const Buckets& B, uint8_t* cbucket,
-                         int32_t* rowlen, Ctl* ctl, hipStream_t s) {
-    if (ncom > 0) k_agg_classify<<<blocks_for(ncom, 256), 256, 0, s>>>(ncom, hoff, bound_cap, B, cbucket, rowlen, ctl);
-}
-void launch_agg_fill(int64_t ncom, const uint8_t* cbucket, int32_t* alist, const int64_t* seg, Ctl* ctl,
-                     hipStream_t s) {
-    if (ncom > 0) k_agg_fill<<<blocks_for(ncom, 256), 256, 0, s>>>(ncom, cbucket, alist, seg, ctl);
-}
-void launch_agg_caps(const int32_t* list, int32_t count, const int64_t* hoff, int64_t bound_cap, int64_t* caps,
-                     hipStream_t s) {
-    if (count > 0) k_agg_caps<<<blocks_for(count, 256), 256, 0, s>>>(list, count, hoff, bound_cap, caps);
+void bucketize_communities(int64_t ncom, const int64_t* hoff, int64_t bound_cap, const Buckets& B, int32_t* rowlen,
+                           int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
+                           hipStream_t s) {
+    constexpr int NB = NB_AGG + 1;
+    if (ncom <= 0) {
+        hipMemsetAsync(totals, 0, NB * sizeof(int32_t), s);
+        return;
+    }
+    hipMemsetAsync(rowlen, 0, (size_t)(ncom + 1) * sizeof(int32_t), s);
+    const int64_t nb = bucket_blocks(ncom);
+    AggBucket bf{hoff, bound_cap, B};
+    k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, ncom, blkcnt, nb);
+    scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
+    k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, ncom, blkoff, nb, out);
+    k_bucket_totals<<<1, 32, 0, s>>>(blkoff, nb, NB, totals);
 }
 
 void launch_aggregate(const LevelView& L, int bucket, const AggArgs& a, const int32_t* list, int32_t count,
@@ -448,15 +572,35 @@ void launch_aggregate(const LevelView& L, int bucket, const AggArgs& a, const in
     });
 }
 
-void launch_aggregate_hub(const LevelView& L, const AggArgs& a, const int32_t* list, int32_t count, hipStream_t s) {
+void launch_member_deg(const LevelView& L, const int32_t* members, int64_t n, int64_t* md, hipStream_t s) {
+    if (n <= 0) return;
+    if (L.t.off64) k_member_deg<int64_t><<<blocks_for(n, 256), 256, 0, s>>>((const int64_t*)L.off, members, n, md);
+    else k_member_deg<int32_t><<<blocks_for(n, 256), 256, 0, s>>>((const int32_t*)L.off, members, n, md);
+}
+void launch_big_info(const int32_t* list, int32_t nbig, const int64_t* hoff, int64_t ncom, int64_t* nch,
+                     int64_t* cap, hipStream_t s) {
+    if (nbig > 0) k_big_info<<<blocks_for(nbig, 256), 256, 0, s>>>(list, nbig, hoff, ncom, nch, cap);
+}
+void launch_big_clear(int32_t* keys, void* vals, int64_t count, hipStream_t s) {
     if (count <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>(8192, (count + 255) / 256);
+    k_big_clear<<<grid, 256, 0, s>>>(keys, (u64*)vals, count);
+}
+void launch_big_insert(const LevelView& L, const BigArgs& a, int64_t nchunks, hipStream_t s) {
+    if (nchunks <= 0) return;
     dispatch_types(L.t, [&](auto o, auto w, auto ac) {
         using OffT = typename decltype(o)::type;
         constexpr int WK = decltype(w)::value;
         using AccT = typename decltype(ac)::type;
         Graph<OffT, WK> g{(const OffT*)L.off, L.idx, L.w};
-        k_aggregate_hub<OffT, WK, AccT><<<(unsigned)count, 1024, 0, s>>>(g, a, list, count);
+        k_big_insert<OffT, WK, AccT><<<(unsigned)nchunks, 1024, 0, s>>>(g, a);
     });
+}
+void launch_big_extract(const LevelView& L, const BigArgs& a, hipStream_t s) {
+    if (a.nbig <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>(BIG_EXTRACT_BLOCKS, a.nbig);
+    if (L.t.acc64) k_big_extract<u64><<<grid, 1024, 0, s>>>(a);
+    else k_big_extract<uint32_t><<<grid, 1024, 0, s>>>(a);
 }
 
 void launch_compact(int64_t ncom, const int64_t* hoff, const int32_t* hidx, const void* hw, const void* goff,

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "louvain.h"
+#include "lv_bucket.h"
 #include "lv_internal.h"
 
 using namespace lv;
@@ -42,6 +43,8 @@ struct Layout {
     size_t ctl, seg, C, Cp, K, Sig, mark, vbucket, blist, qa, qb, movers, hcaps, hpre;
     size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
     size_t hidx, hw, sup_off[2], sup_idx[2], sup_w[2], pool_keys, pool_vals, scan;
+    size_t md, mpos, bnch, bchpre, bitmaps, hubpos, blkcnt, blkoff;
+    int64_t bitmap_words;
     int64_t pool_entries;
     size_t total;
 };
@@ -89,6 +92,15 @@ bool make_layout(int64_t n, int64_t m, Layout* L) {
     L->pool_keys = take((size_t)pool * 4);
     L->pool_vals = take((size_t)pool * 8);
     L->scan = take(scan_scratch_bytes(n + 2));
+    L->hubpos = take(N * 4);
+    L->blkcnt = take((size_t)(MAX_BUCKETS * (bucket_blocks(n + 1) + 1) + 8) * 4);
+    L->blkoff = take((size_t)(MAX_BUCKETS * (bucket_blocks(n + 1) + 1) + 8) * 4);
+    L->md = take((N + 1) * 8);
+    L->mpos = take((N + 2) * 8);
+    L->bnch = take((N + 1) * 8);
+    L->bchpre = take((N + 2) * 8);
+    L->bitmap_words = (n + 32) / 32;
+    L->bitmaps = take((size_t)BIG_EXTRACT_BLOCKS * (size_t)L->bitmap_words * 4);
     L->total = o;
     return true;
 }
@@ -100,10 +112,11 @@ struct KRec {
 };
 
 enum KName { K_MOVE0 = 0, K_MOVE1, K_MOVE2, K_MOVE3, K_MOVE4, K_MOVE_HUB, K_SYNC_APPLY, K_PASS_INIT, K_AGG_PREP,
-             K_AGG0, K_AGG1, K_AGG2, K_AGG3, K_AGG_HUB, K_COMPACT, K_COUNT };
+             K_AGG0, K_AGG1, K_AGG2, K_AGG3, K_AGG_BIG_INSERT, K_AGG_BIG_EXTRACT, K_COMPACT, K_QUEUE, K_COUNT };
 const char* KNAMES[K_COUNT] = {"move_b0", "move_b1", "move_b2", "move_b3", "move_b4", "move_hub", "sync_apply",
                                "pass_init", "aggregate_prep", "aggregate_b0", "aggregate_b1", "aggregate_b2",
-                               "aggregate_b3", "aggregate_hub", "compact"};
+                               "aggregate_b3", "aggregate_big_insert", "aggregate_big_extract", "compact",
+                               "queue_build"};
 
 }  // namespace
 
@@ -229,11 +242,21 @@ int64_t move_alg_bytes(const LevelView& L, uint64_t eval, uint64_t arcs, uint64_
     return b;
 }
 
-struct IterRead {
-    u64 s_lo, s_hi, moves, pad0, pad1, pad2;
+// Sum of the striped per-iteration counters.
+struct IterTotals {
+    unsigned __int128 S;
+    uint64_t moves;
     int32_t qcount[MAX_BUCKETS];
-    int32_t movers, err;
 };
+IterTotals sum_iter(const Ctl& c) {
+    IterTotals t{};
+    for (int k = 0; k < STRIPES; k++) {
+        t.S += ((unsigned __int128)c.s_hi[k] << 64) + (unsigned __int128)c.s_lo[k];
+        t.moves += c.moves[k];
+    }
+    for (int b = 0; b < MAX_BUCKETS; b++) t.qcount[b] = c.qcount[b];
+    return t;
+}
 
 }  // namespace
 
@@ -253,6 +276,10 @@ void louvain_params_default(louvain_params* p) {
     p->mode = LOUVAIN_ASYNC;
     p->pruner = LOUVAIN_PRUNE_FLAGS;
     p->validate = 1;
+    p->async_coherent = 1;
+    p->bucket_order = 0;
+    p->async_slices = 64;
+    p->async_slice_iters = 0;
 }
 
 louvain_status louvain_workspace_size(const louvain_graph* g, const louvain_params* p, size_t* bytes) {
@@ -383,15 +410,6 @@ struct Runner {
         return LOUVAIN_OK;
     }
 
-    // Upload per-bucket segment starts (host prefix of counts) to seg[base..].
-    louvain_status upload_seg(int base, const int64_t* segs, int count) {
-        int64_t* up = (int64_t*)h->pinned_up + base;
-        memcpy(up, segs, count * sizeof(int64_t));
-        HIPCHK(h, hipMemcpyAsync(at<int64_t>(h->lay.seg) + base, up, count * sizeof(int64_t),
-                                 hipMemcpyHostToDevice, s));
-        return LOUVAIN_OK;
-    }
-
     // Split the hub list into chunks whose table capacities fit the pool.
     // Fails if one table alone exceeds the pool (cannot happen for
     // capacities bounded by 2 * n, which the pool always holds).
@@ -428,13 +446,14 @@ louvain_status Runner::run() {
     uint8_t* vb = at<uint8_t>(Y.vbucket);
     int32_t* blist = at<int32_t>(Y.blist);
     int32_t* qbuf[2] = {at<int32_t>(Y.qa), at<int32_t>(Y.qb)};
-    int64_t* seg = at<int64_t>(Y.seg);
+    int32_t* hubpos = at<int32_t>(Y.hubpos);
+    int32_t* blkcnt = at<int32_t>(Y.blkcnt);
+    int32_t* blkoff = at<int32_t>(Y.blkoff);
     void* scan = at<void>(Y.scan);
 
     memset(&H->st, 0, sizeof(H->st));
     H->recs.clear();
     H->evnext = 0;
-    for (int k = 0; k < K_COUNT; k++) { H->kms[k] = 0; H->klaunch[k] = 0; H->kbytes[k] = 0; }
     HIPCHK(H, hipMemsetAsync(ctl(), 0, sizeof(Ctl), s));
     iota_i32(C, n0, s);
 
@@ -451,28 +470,27 @@ louvain_status Runner::run() {
         have_newid = false;
         // ---------------- pass init: classify, bucket lists, K', Sigma'
         HIPCHK(H, hipMemsetAsync(&ctl()->kmax, 0, sizeof(u64), s));
-        HIPCHK(H, hipMemsetAsync(ctl()->bcount, 0, 2 * MAX_BUCKETS * sizeof(int32_t), s));
-        int32_t bcount[MAX_BUCKETS];
-        timed(H, K_PASS_INIT, 0, [&] { launch_classify(L, H->mb, vb, Cp, K, Sig, ctl(), s); });
-        if ((st = readback(H, bcount, ctl()->bcount, sizeof(bcount))) != LOUVAIN_OK) return st;
         const int NBT = NB_MOVE + 1;  // LDS buckets + hub
+        int32_t bcount[MAX_BUCKETS] = {};
+        timed(H, K_PASS_INIT, 0, [&] {
+            launch_classify(L, H->mb, vb, Cp, K, Sig, s);
+            bucketize_vertices(n, vb, mark, 0, 0, blkcnt, blkoff, blist, ctl()->bcount, scan, s);
+        });
+        if ((st = readback(H, bcount, ctl()->bcount, NBT * sizeof(int32_t))) != LOUVAIN_OK) return st;
         int64_t segs[MAX_BUCKETS + 1];
         segs[0] = 0;
         for (int b = 0; b < NBT; b++) segs[b + 1] = segs[b] + bcount[b];
         const int64_t nonisolated = segs[NBT];
-        if ((st = upload_seg(0, segs, NBT + 1)) != LOUVAIN_OK) return st;
         timed(H, K_PASS_INIT, 0, [&] {
-            launch_fill_buckets(n, vb, blist, seg, ctl(), s);
             for (int b = 0; b < NBT; b++)
                 launch_rowsum(L, b, blist + segs[b], bcount[b], K, Sig, ctl(), s);
         });
-        // hub tables
+        // hub tables: static positions in ascending vertex order
         const int32_t nhub = bcount[NB_MOVE];
-        const int32_t* hub_list = blist + segs[NB_MOVE];
         int64_t* hpre = at<int64_t>(Y.hpre);
         std::vector<std::pair<int32_t, int32_t>> hub_chunks;
         if (nhub > 0) {
-            launch_hub_caps(L, hub_list, nhub, at<int64_t>(Y.hcaps), s);
+            launch_hub_caps(L, blist + segs[NB_MOVE], nhub, at<int64_t>(Y.hcaps), hubpos, s);
             scan_i64_to_i64(at<int64_t>(Y.hcaps), hpre, nhub, scan, s);
             hub_pre.resize(nhub + 1);
             if ((st = readback(H, hub_pre.data(), hpre, (nhub + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
@@ -488,14 +506,16 @@ louvain_status Runner::run() {
         // ---------------- local moving
         int32_t li = P.max_iterations;
         int32_t counts[MAX_BUCKETS + 1];
+        int64_t csegs[MAX_BUCKETS + 1];
         for (int b = 0; b < NBT; b++) counts[b] = bcount[b];
+        for (int b = 0; b <= NBT; b++) csegs[b] = segs[b];
         const int32_t* cur_list = blist;  // iteration 0: every vertex with an arc
         int qsel = 0;
         u64 prev_b[5][MAX_BUCKETS] = {};
+        const int mode = sync ? 0 : (P.async_coherent ? 2 : 1);
         for (int t = 0; t < P.max_iterations; t++) {
             const int pl = P.pick_less > 0 && ((t + P.pick_less / 2) % P.pick_less) == 0;
-            HIPCHK(H, hipMemsetAsync(ctl(), 0, offsetof(Ctl, err), s));
-            const uint32_t stamp_cur = H->stamp;
+            HIPCHK(H, hipMemsetAsync(ctl(), 0, CTL_ITER_BYTES, s));
             const uint32_t stamp_next = ++H->stamp;
             int32_t* qnext = qbuf[qsel];
             MoveArgs a{};
@@ -509,81 +529,100 @@ louvain_status Runner::run() {
             a.wide = wide;
             a.pl = pl;
             a.prune = prune;
-            a.check_mark = (t > 0 && prune) ? 1 : 0;
-            a.stamp_cur = stamp_cur;
             a.stamp_next = stamp_next;
             a.mark = mark;
-            a.vbucket = vb;
-            a.qnext = qnext;
-            a.qseg = seg;
             a.ctl = ctl();
             a.movers = at<int32_t>(Y.movers);
+            a.hubpos = hubpos;
+            a.hub_pre = hpre;
             a.hub_keys = at<int32_t>(Y.pool_keys);
             a.hub_vals = at<void>(Y.pool_vals);
-            a.hub_off = hpre;
-            for (int b = 0; b < NB_MOVE; b++) {
-                if (counts[b] <= 0) continue;
-                a.bucket = b;
-                timed(H, K_MOVE0 + b, 0, [&] { launch_move(LM, b, sync, a, cur_list + segs[b], counts[b], s); });
-            }
-            // hubs: always walk the static hub list; unqueued hubs exit at once
-            if (nhub > 0 && (t == 0 || !prune || counts[NB_MOVE] > 0)) {
-                a.bucket = NB_MOVE;
-                for (auto& ch : hub_chunks) {
-                    a.hub_off = hpre + ch.first;
-                    a.hub_base = hub_pre[ch.first];
-                    timed(H, K_MOVE_HUB, 0,
-                          [&] { launch_move_hub(LM, sync, a, hub_list + ch.first, ch.second - ch.first, s); });
+            // slice sl of a bucket segment: [cnt*sl/ns, cnt*(sl+1)/ns)
+            const bool slice_now = P.async_slice_iters <= 0 || t < P.async_slice_iters;
+            const int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
+            for (int sl = 0; sl < ns; sl++) {
+                auto lo_of = [&](int b) { return (int32_t)((int64_t)counts[b] * sl / ns); };
+                auto hi_of = [&](int b) { return (int32_t)((int64_t)counts[b] * (sl + 1) / ns); };
+                auto run_hubs = [&] {
+                    const int32_t lo = lo_of(NB_MOVE), hi = hi_of(NB_MOVE);
+                    if (hi <= lo) return;
+                    a.bucket = NB_MOVE;
+                    for (auto& ch : hub_chunks) {
+                        a.chunk_lo = ch.first;
+                        a.chunk_hi = ch.second;
+                        timed(H, K_MOVE_HUB, 0,
+                              [&] { launch_move_hub(LM, mode, a, cur_list + csegs[NB_MOVE] + lo, hi - lo, s); });
+                    }
+                };
+                if (P.bucket_order) run_hubs();
+                for (int k = 0; k < NB_MOVE; k++) {
+                    const int b = P.bucket_order ? NB_MOVE - 1 - k : k;
+                    const int32_t lo = lo_of(b), hi = hi_of(b);
+                    if (hi <= lo) continue;
+                    a.bucket = b;
+                    timed(H, K_MOVE0 + b, 0,
+                          [&] { launch_move(LM, b, mode, a, cur_list + csegs[b] + lo, hi - lo, s); });
                 }
-                a.hub_off = hpre;
+                if (!P.bucket_order) run_hubs();
             }
             if (sync) timed(H, K_SYNC_APPLY, 0, [&] { launch_sync_apply(L, a, s); });
-            // read back the iteration's totals and per-bucket counters
-            struct {
-                IterRead it;
-            } rb;
-            if ((st = readback(H, &rb.it, ctl(), sizeof(IterRead))) != LOUVAIN_OK) return st;
-            u64 bc[5][MAX_BUCKETS];
-            if ((st = readback(H, bc, ctl()->b_eval, sizeof(bc))) != LOUVAIN_OK) return st;
-            const unsigned __int128 S = ((unsigned __int128)rb.it.s_hi << 64) | rb.it.s_lo;
+            if (prune)
+                timed(H, K_QUEUE, 0, [&] {
+                    bucketize_vertices(n, vb, mark, stamp_next, 1, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
+                });
+            // read back the iteration's striped totals
+            Ctl* hc = (Ctl*)H->pinned;
+            HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
+            if (H->prof) HIPCHK(H, hipMemcpyAsync(&hc->bstat, &ctl()->bstat, sizeof(hc->bstat), hipMemcpyDeviceToHost, s));
+            HIPCHK(H, hipStreamSynchronize(s));
+            const IterTotals it = sum_iter(*hc);
+            const unsigned __int128 S = it.S;
             H->st.iterations++;
-            H->st.moves += (int64_t)rb.it.moves;
+            H->st.moves += (int64_t)it.moves;
             // algorithmic bytes of this iteration's move launches, per bucket
             if (H->prof) {
                 for (int b = 0; b < NBT; b++) {
-                    const u64 de = bc[0][b] - prev_b[0][b], da = bc[1][b] - prev_b[1][b],
-                              dd = bc[2][b] - prev_b[2][b], dm = bc[3][b] - prev_b[3][b],
-                              dma = bc[4][b] - prev_b[4][b];
-                    if (!de) continue;
-                    const int64_t bytes = move_alg_bytes(LM, de, da, dd, dm, dma, sync);
-                    const int kind = b < NB_MOVE ? K_MOVE0 + b : K_MOVE_HUB;
-                    for (auto it = H->recs.rbegin(); it != H->recs.rend(); ++it)
-                        if (it->kind == kind) { it->bytes += bytes; break; }
+                    u64 cur[5];
+                    for (int q = 0; q < 5; q++) {
+                        cur[q] = 0;
+                        for (int k = 0; k < STRIPES; k++) cur[q] += hc->bstat[q][b][k];
+                    }
+                    const u64 de = cur[0] - prev_b[0][b];
+                    if (de) {
+                        const int64_t bytes = move_alg_bytes(LM, de, cur[1] - prev_b[1][b], cur[2] - prev_b[2][b],
+                                                             cur[3] - prev_b[3][b], cur[4] - prev_b[4][b], sync);
+                        const int kind = b < NB_MOVE ? K_MOVE0 + b : K_MOVE_HUB;
+                        for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
+                            if (r->kind == kind) { r->bytes += bytes; break; }
+                    }
+                    for (int q = 0; q < 5; q++) prev_b[q][b] = cur[q];
                 }
             }
-            memcpy(prev_b, bc, sizeof(bc));
             if (H->itfn) {
                 hcp.resize(n);
                 hsig.resize(n);
                 if ((st = readback(H, hcp.data(), Cp, n * 4)) != LOUVAIN_OK) return st;
                 if ((st = readback(H, hsig.data(), Sig, n * 8)) != LOUVAIN_OK) return st;
-                H->itfn(H->user, pass, t, n, hcp.data(), hsig.data(), (int64_t)rb.it.moves, (int64_t)rb.it.s_hi,
-                        rb.it.s_lo);
+                H->itfn(H->user, pass, t, n, hcp.data(), hsig.data(), (int64_t)it.moves, (int64_t)(S >> 64),
+                        (uint64_t)S);
             }
             if (converged(S, W, P, pass)) { li = t + 1; break; }
             // next iteration's queue
             if (prune) {
                 int64_t total = 0;
-                for (int b = 0; b < NBT; b++) { counts[b] = rb.it.qcount[b]; total += counts[b]; }
+                csegs[0] = 0;
+                for (int b = 0; b < NBT; b++) {
+                    counts[b] = it.qcount[b];
+                    total += counts[b];
+                    csegs[b + 1] = csegs[b] + counts[b];
+                }
                 cur_list = qnext;
                 qsel ^= 1;
                 if (total == 0) {
                     // nothing flagged: the next iteration has S = 0 and converges
                     if (t + 1 >= P.max_iterations) { li = P.max_iterations; break; }
                     H->st.iterations++;
-                    if (H->itfn) {
-                        H->itfn(H->user, pass, t + 1, n, hcp.data(), hsig.data(), 0, 0, 0);
-                    }
+                    if (H->itfn) H->itfn(H->user, pass, t + 1, n, hcp.data(), hsig.data(), 0, 0, 0);
                     li = t + 2;
                     break;
                 }
@@ -625,7 +664,7 @@ louvain_status Runner::run() {
         HIPCHK(H, hipMemsetAsync(cnt, 0, (ncom + 1) * 4, s));
         HIPCHK(H, hipMemsetAsync(cursor, 0, (ncom + 1) * 4, s));
         HIPCHK(H, hipMemsetAsync(cdeg, 0, (ncom + 1) * 8, s));
-        HIPCHK(H, hipMemsetAsync(ctl()->bcount, 0, 2 * MAX_BUCKETS * sizeof(int32_t), s));
+        int32_t* alist = at<int32_t>(Y.alist);
         timed(H, K_AGG_PREP, 0, [&] {
             launch_relabel(Cp, n, newid, s);
             launch_dendrogram(C, n0, Cp, s);
@@ -633,18 +672,15 @@ louvain_status Runner::run() {
             scan_i32_to_i32(cnt, coff, ncom, scan, s);
             scan_i64_to_i64(cdeg, hoff, ncom, scan, s);
             launch_comm_fill(n, Cp, coff, cursor, members, s);
-            launch_agg_classify(ncom, hoff, ncom, H->ab, at<uint8_t>(Y.cbucket), at<int32_t>(Y.rowlen), ctl(), s);
+            bucketize_communities(ncom, hoff, ncom, H->ab, at<int32_t>(Y.rowlen), blkcnt, blkoff, alist,
+                                  ctl()->bcount, scan, s);
         });
-        int32_t acount[MAX_BUCKETS];
-        if ((st = readback(H, acount, ctl()->bcount, sizeof(acount))) != LOUVAIN_OK) return st;
+        int32_t acount[MAX_BUCKETS] = {};
         const int NBA = NB_AGG + 1;
+        if ((st = readback(H, acount, ctl()->bcount, NBA * sizeof(int32_t))) != LOUVAIN_OK) return st;
         int64_t asegs[MAX_BUCKETS + 1];
         asegs[0] = 0;
         for (int b = 0; b < NBA; b++) asegs[b + 1] = asegs[b] + acount[b];
-        if ((st = upload_seg(16, asegs, NBA + 1)) != LOUVAIN_OK) return st;
-        int32_t* alist = at<int32_t>(Y.alist);
-        timed(H, K_AGG_PREP, 0,
-              [&] { launch_agg_fill(ncom, at<uint8_t>(Y.cbucket), alist, seg + 16, ctl(), s); });
 
         // ---------------- super-row hashing into the holey buffer
         const int nxt = cur_sup ^ 1;
@@ -657,29 +693,61 @@ louvain_status Runner::run() {
         A.hw = at<void>(Y.hw);
         A.rowlen = at<int32_t>(Y.rowlen);
         A.out_w64 = H->sup_wk == 2;
-        A.hub_keys = at<int32_t>(Y.pool_keys);
-        A.hub_vals = at<void>(Y.pool_vals);
         LevelView LA = L;
         LA.t.acc64 = (u64)W >= ((u64)1 << 32);
         for (int b = 0; b < NB_AGG; b++) {
             if (acount[b] <= 0) continue;
             timed(H, K_AGG0 + b, 0, [&] { launch_aggregate(LA, b, A, alist + asegs[b], acount[b], s); });
         }
-        const int32_t nah = acount[NB_AGG];
-        if (nah > 0) {
-            const int32_t* ah_list = alist + asegs[NB_AGG];
-            launch_agg_caps(ah_list, nah, hoff, ncom, at<int64_t>(Y.hcaps), s);
-            scan_i64_to_i64(at<int64_t>(Y.hcaps), hpre, nah, scan, s);
-            hub_pre.resize(nah + 1);
-            if ((st = readback(H, hub_pre.data(), hpre, (nah + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
-            std::vector<std::pair<int32_t, int32_t>> ach;
-            if (!chunks(hub_pre, Y.pool_entries, &ach))
+        const int32_t nbig = acount[NB_AGG];
+        if (nbig > 0) {
+            // big communities: virtual-arc positions, chunk and table prefixes
+            const int32_t* big_list = alist + asegs[NB_AGG];
+            int64_t* md = at<int64_t>(Y.md);
+            int64_t* mpos = at<int64_t>(Y.mpos);
+            int64_t* bnch = at<int64_t>(Y.bnch);
+            int64_t* bchpre = at<int64_t>(Y.bchpre);
+            timed(H, K_AGG_PREP, 0, [&] {
+                launch_member_deg(L, members, n, md, s);
+                scan_i64_to_i64(md, mpos, n, scan, s);
+                launch_big_info(big_list, nbig, hoff, ncom, bnch, at<int64_t>(Y.hcaps), s);
+                scan_i64_to_i64(bnch, bchpre, nbig, scan, s);
+                scan_i64_to_i64(at<int64_t>(Y.hcaps), hpre, nbig, scan, s);
+            });
+            std::vector<int64_t> chpre(nbig + 1);
+            hub_pre.resize(nbig + 1);
+            if ((st = readback(H, chpre.data(), bchpre, (nbig + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
+            if ((st = readback(H, hub_pre.data(), hpre, (nbig + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
+            std::vector<std::pair<int32_t, int32_t>> groups;
+            if (!chunks(hub_pre, Y.pool_entries, &groups))
                 return fail(H, LOUVAIN_ERR_WORKSPACE, "community hash table exceeds the workspace pool");
-            for (auto& ch : ach) {
-                A.hub_off = hpre + ch.first;
-                A.hub_base = hub_pre[ch.first];
-                timed(H, K_AGG_HUB, 0,
-                      [&] { launch_aggregate_hub(LA, A, ah_list + ch.first, ch.second - ch.first, s); });
+            for (auto& gr : groups) {
+                BigArgs B{};
+                B.list = big_list + gr.first;
+                B.nbig = gr.second - gr.first;
+                B.chunk_pre = bchpre + gr.first;
+                B.chunk_base = chpre[gr.first];
+                B.tab_pre = hpre + gr.first;
+                B.tab_base = hub_pre[gr.first];
+                B.Cp = Cp;
+                B.coff = coff;
+                B.members = members;
+                B.mpos = mpos;
+                B.hoff = hoff;
+                B.keys = at<int32_t>(Y.pool_keys);
+                B.vals = at<void>(Y.pool_vals);
+                B.hidx = A.hidx;
+                B.hw = A.hw;
+                B.out_w64 = A.out_w64;
+                B.rowlen = A.rowlen;
+                B.bitmaps = at<uint32_t>(Y.bitmaps);
+                B.words = (ncom + 31) / 32;
+                const int64_t nchunks = chpre[gr.second] - chpre[gr.first];
+                timed(H, K_AGG_BIG_INSERT, 0, [&] {
+                    launch_big_clear(B.keys, B.vals, hub_pre[gr.second] - hub_pre[gr.first], s);
+                    launch_big_insert(LA, B, nchunks, s);
+                });
+                timed(H, K_AGG_BIG_EXTRACT, 0, [&] { launch_big_extract(LA, B, s); });
             }
         }
         // ---------------- compaction into the next super-graph
@@ -791,11 +859,12 @@ louvain_status louvain_run(louvain_t* h) {
     }
     Ctl c;
     if (readback(h, &c, h->ctl(), sizeof(Ctl)) == LOUVAIN_OK) {
-        for (int b = 0; b < MAX_BUCKETS; b++) {
-            h->st.vertices_evaluated += (int64_t)c.b_eval[b];
-            h->st.arcs_scanned += (int64_t)c.b_arcs[b];
-            h->st.distinct_scanned += (int64_t)c.b_distinct[b];
-        }
+        for (int b = 0; b < MAX_BUCKETS; b++)
+            for (int k = 0; k < STRIPES; k++) {
+                h->st.vertices_evaluated += (int64_t)c.bstat[0][b][k];
+                h->st.arcs_scanned += (int64_t)c.bstat[1][b][k];
+                h->st.distinct_scanned += (int64_t)c.bstat[2][b][k];
+            }
     }
     h->ran = true;
     return LOUVAIN_OK;
@@ -843,6 +912,7 @@ louvain_status louvain_get_stats(louvain_t* h, louvain_stats* s) {
 louvain_status louvain_set_profiling(louvain_t* h, int32_t enable) {
     if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
     h->prof = enable != 0;
+    for (int k = 0; k < K_COUNT; k++) { h->kms[k] = 0; h->klaunch[k] = 0; h->kbytes[k] = 0; }
     return LOUVAIN_OK;
 }
 

@@ -9,6 +9,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace lv {
@@ -22,32 +23,32 @@ typedef long long i64;
 typedef __int128 i128;
 
 // Device control block: counters written by kernels and read back by the host.
+// Hot counters are striped over STRIPES slots (a block uses slot
+// blockIdx % STRIPES) so that thousands of blocks do not serialise on one
+// address; the host adds the stripes.
+constexpr int STRIPES = 32;
 struct Ctl {
-    u64 s_lo;               // 128-bit sum of applied gains of the current iteration (two's complement)
-    u64 s_hi;
-    u64 moves;              // moves applied in the current iteration
-    u64 unused0;
-    u64 unused1;
-    u64 unused2;
+    // ---- zeroed before every local-moving iteration
     int32_t qcount[MAX_BUCKETS];  // next-iteration queue sizes, per move bucket
-    int32_t movers;         // SYNC: number of (vertex, target) pairs recorded
-    int32_t err;            // validation error bits
-    u64 kmax;               // largest weighted degree of the level
-    u64 wsum;               // total weight (validation pass)
-    int32_t bcount[MAX_BUCKETS];   // bucket sizes (classification)
-    int32_t bcursor[MAX_BUCKETS];  // fill cursors
-    u64 q_lo;               // modularity numerator accumulator (128-bit)
+    int32_t movers;               // SYNC: number of (vertex, target) pairs recorded
+    int32_t pad0;
+    u64 s_lo[STRIPES];            // 128-bit sums of applied gains (two's complement)
+    u64 s_hi[STRIPES];
+    u64 moves[STRIPES];           // moves applied
+    // ---- other state
+    int32_t err;                  // validation error bits
+    int32_t nonisolated;
+    u64 kmax;                     // largest weighted degree of the level
+    u64 wsum;                     // total weight (validation pass)
+    int32_t bcount[MAX_BUCKETS];  // bucket sizes (classification)
+    int32_t bcursor[MAX_BUCKETS]; // fill cursors
+    u64 q_lo;                     // modularity numerator accumulator (128-bit)
     u64 q_hi;
-    int32_t nonisolated;    // vertices of the level with at least one arc
-    int32_t pad[3];
-    // per-bucket run totals (move buckets, last = hub): evaluations, arcs,
+    // ---- run totals per move bucket (last = hub): evaluations, arcs,
     // distinct communities, moves, arcs of movers
-    u64 b_eval[MAX_BUCKETS];
-    u64 b_arcs[MAX_BUCKETS];
-    u64 b_distinct[MAX_BUCKETS];
-    u64 b_moves[MAX_BUCKETS];
-    u64 b_marcs[MAX_BUCKETS];
+    u64 bstat[5][MAX_BUCKETS][STRIPES];
 };
+constexpr size_t CTL_ITER_BYTES = offsetof(Ctl, err);
 
 // CSR view of one level.  WK: 0 = unit weights, 1 = int32, 2 = int64.
 template <typename OffT, int WK>
@@ -109,23 +110,26 @@ __device__ __forceinline__ bool better(KeyT k1, int32_t d1, KeyT k2, int32_t d2)
     return k1 > k2 || (k1 == k2 && d1 < d2);
 }
 
-// Butterfly reduction inside an aligned group of G <= 64 lanes.
+// Butterfly reduction inside an aligned group of G <= 64 lanes; the winner's
+// payload v (its K_{i->d}) travels with it.
 template <int G>
-__device__ __forceinline__ void group_best64(i64& key, int32_t& d) {
+__device__ __forceinline__ void group_best64(i64& key, int32_t& d, i64& v) {
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1) {
         i64 k2 = shfl_xor64(key, m, G);
         int32_t d2 = __shfl_xor(d, m, G);
-        if (better(k2, d2, key, d)) { key = k2; d = d2; }
+        i64 v2 = shfl_xor64(v, m, G);
+        if (better(k2, d2, key, d)) { key = k2; d = d2; v = v2; }
     }
 }
 template <int G>
-__device__ __forceinline__ void group_best128(i128& key, int32_t& d) {
+__device__ __forceinline__ void group_best128(i128& key, int32_t& d, i64& v) {
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1) {
         i128 k2 = shfl_xor128(key, m, G);
         int32_t d2 = __shfl_xor(d, m, G);
-        if (better(k2, d2, key, d)) { key = k2; d = d2; }
+        i64 v2 = shfl_xor64(v, m, G);
+        if (better(k2, d2, key, d)) { key = k2; d = d2; v = v2; }
     }
 }
 template <int G>
@@ -160,27 +164,6 @@ __device__ __forceinline__ void group_sync() {
     } else {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-    }
-}
-
-// Wave-aggregated append of `item` to per-bucket queue segments:
-// queue[seg[b] + atomicAdd(count[b], .)] = item, one atomic per bucket per wave.
-__device__ __forceinline__ void wave_enqueue(bool want, int b, int32_t item, int32_t* queue, const int64_t* seg,
-                                             int32_t* count) {
-    const int lane = __lane_id();
-    u64 pending = __ballot(want);
-    while (pending) {
-        int leader = __ffsll((long long)pending) - 1;
-        int lb = __shfl(b, leader);
-        u64 same = __ballot(want && b == lb);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&count[lb], __popcll(same));
-        base = __shfl(base, leader);
-        if (want && b == lb) {
-            int rank = __popcll(same & ((1ull << lane) - 1ull));
-            queue[seg[lb] + base + rank] = item;
-        }
-        pending &= ~same;
     }
 }
 

@@ -50,22 +50,18 @@ struct MoveArgs {
     i64 W;                // total weight (2m)
     int32_t wide;         // 1: 128-bit gain arithmetic
     int32_t pl;           // Pick-Less active this iteration
-    int32_t prune;        // 1: mark neighbours of movers for the next iteration
-    int32_t check_mark;   // hub path: skip vertices whose mark != stamp_cur
-    uint32_t stamp_cur;   // stamp of vertices queued for this iteration
-    uint32_t stamp_next;  // stamp for the next iteration's queue
+    int32_t prune;        // 1: stamp neighbours of movers for the next iteration
+    uint32_t stamp_next;  // stamp marking membership of the next iteration's queue
     uint32_t* mark;
-    const uint8_t* vbucket;
-    int32_t* qnext;
-    const int64_t* qseg;  // per-bucket segment start in queues (device)
     Ctl* ctl;
     int32_t* movers;      // SYNC: (vertex, target) pairs
     int32_t bucket;       // bucket id for per-bucket counters
-    int32_t log2cap;      // hub path: unused (per-vertex)
-    int32_t* hub_keys;    // hub path: table pool
+    // hub path
+    const int32_t* hubpos;   // static hub position of each hub vertex
+    const int64_t* hub_pre;  // prefix of hub table capacities over static positions
+    int32_t chunk_lo, chunk_hi;  // static positions whose tables are in the pool for this launch
+    int32_t* hub_keys;
     void* hub_vals;
-    const int64_t* hub_off;  // hub path: table offsets (per hub list entry, chunk-relative base subtracted)
-    int64_t hub_base;
 };
 
 struct Buckets {
@@ -84,15 +80,21 @@ void iota_i32(int32_t* p, int64_t n, hipStream_t s);
 
 // ---- launchers: pass init and local moving (lv_move.hip)
 void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int32_t* Cp, i64* K, i64* Sig,
-                     Ctl* ctl, hipStream_t s);
-void launch_fill_buckets(int64_t n, const uint8_t* vbucket, int32_t* blist, const int64_t* seg, Ctl* ctl,
-                         hipStream_t s);
+                     hipStream_t s);
+// Ordered partition of the level's vertices into NB_MOVE+1 bucket segments
+// (all vertices with arcs, or those whose mark equals `stamp`); bucket totals
+// go to totals[0..NB_MOVE].  blkcnt/blkoff: (NB_MOVE+1) * bucket_blocks(n) (+1).
+void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint32_t* mark, uint32_t stamp, int use_mark,
+                        int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
+                        hipStream_t s);
 void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t count, i64* K, i64* Sig, Ctl* ctl,
                    hipStream_t s);
-void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, hipStream_t s);
-void launch_move(const LevelView& L, int bucket, int sync, const MoveArgs& a, const int32_t* list, int32_t count,
+void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, int32_t* hubpos,
+                     hipStream_t s);
+// mode: 0 = SYNC, 1 = ASYNC with cached loads, 2 = ASYNC with device-coherent loads/stores
+void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
                  hipStream_t s);
-void launch_move_hub(const LevelView& L, int sync, const MoveArgs& a, const int32_t* list, int32_t count,
+void launch_move_hub(const LevelView& L, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
                      hipStream_t s);
 void launch_sync_apply(const LevelView& L, const MoveArgs& a, hipStream_t s);
 
@@ -106,10 +108,6 @@ struct AggArgs {
     void* hw;                // holey weights (int32 or int64, per out_w64)
     int32_t* rowlen;         // distinct count per community
     int32_t out_w64;         // super-graph weights int64
-    int32_t* hub_keys;
-    void* hub_vals;
-    const int64_t* hub_off;
-    int64_t hub_base;
 };
 void launch_mark_used(const int32_t* Cp, int64_t n, int32_t* used, hipStream_t s);
 void launch_relabel(int32_t* Cp, int64_t n, const int32_t* newid, hipStream_t s);
@@ -118,16 +116,46 @@ void launch_final_lookup(int32_t* C, int64_t n0, const int32_t* Cp, const int32_
 void launch_comm_count(const LevelView& L, const int32_t* Cp, int32_t* cnt, int64_t* cdeg, hipStream_t s);
 void launch_comm_fill(int64_t n, const int32_t* Cp, const int32_t* coff, int32_t* cursor, int32_t* members,
                       hipStream_t s);
-void launch_agg_classify(int64_t ncom, const int64_t* hoff, int64_t bound_cap, const Buckets& B, uint8_t* cbucket,
-                         int32_t* rowlen, Ctl* ctl, hipStream_t s);
-void launch_agg_fill(int64_t ncom, const uint8_t* cbucket, int32_t* alist, const int64_t* seg, Ctl* ctl,
-                     hipStream_t s);
-void launch_agg_caps(const int32_t* list, int32_t count, const int64_t* hoff, int64_t bound_cap, int64_t* caps,
-                     hipStream_t s);
+// Ordered partition of communities into NB_AGG LDS buckets + the big path
+// (totals to totals[0..NB_AGG]); zeroes rowlen.
+void bucketize_communities(int64_t ncom, const int64_t* hoff, int64_t bound_cap, const Buckets& B, int32_t* rowlen,
+                           int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
+                           hipStream_t s);
 void launch_aggregate(const LevelView& L, int bucket, const AggArgs& a, const int32_t* list, int32_t count,
                       hipStream_t s);
-void launch_aggregate_hub(const LevelView& L, const AggArgs& a, const int32_t* list, int32_t count,
-                          hipStream_t s);
+
+// Big communities: spread over many workgroups (see lv_aggr.hip).
+constexpr int BIG_CH = 4096;          // virtual arcs per chunk (one workgroup)
+constexpr int BIG_LCAP = 8192;        // LDS table slots per chunk
+constexpr int64_t BIG_ARCS = 32768;   // communities with more arcs always take the big path
+constexpr int BIG_EXTRACT_BLOCKS = 256;
+struct BigArgs {
+    const int32_t* list;       // big communities of this group
+    int32_t nbig;
+    const int64_t* chunk_pre;  // chunk prefix per big community (nbig+1 entries used)
+    int64_t chunk_base;
+    const int64_t* tab_pre;    // table-capacity prefix (nbig+1 entries used)
+    int64_t tab_base;
+    const int32_t* Cp;
+    const int32_t* coff;
+    const int32_t* members;
+    const int64_t* mpos;       // exclusive prefix of member degrees, community-vertex order
+    const int64_t* hoff;
+    int32_t* keys;             // global table pool
+    void* vals;
+    int32_t* hidx;
+    void* hw;
+    int32_t out_w64;
+    int32_t* rowlen;
+    uint32_t* bitmaps;         // BIG_EXTRACT_BLOCKS * words
+    int64_t words;             // ceil(ncom / 32)
+};
+void launch_member_deg(const LevelView& L, const int32_t* members, int64_t n, int64_t* md, hipStream_t s);
+void launch_big_info(const int32_t* list, int32_t nbig, const int64_t* hoff, int64_t ncom, int64_t* nch,
+                     int64_t* cap, hipStream_t s);
+void launch_big_clear(int32_t* keys, void* vals, int64_t count, hipStream_t s);
+void launch_big_insert(const LevelView& L, const BigArgs& a, int64_t nchunks, hipStream_t s);
+void launch_big_extract(const LevelView& L, const BigArgs& a, hipStream_t s);
 void launch_compact(int64_t ncom, const int64_t* hoff, const int32_t* hidx, const void* hw, const void* goff,
                     int goff64, int32_t* gidx, void* gw, int w64, hipStream_t s);
 void launch_rowlen_to_offsets(const int32_t* rowlen, int64_t ncom, void* goff, int goff64, void* scratch,

@@ -15,9 +15,12 @@
 // processed by groups of G lanes per vertex (G = 8 .. 1024) with a private
 // open-addressing table of CAP slots in LDS, or -- above the largest LDS
 // bucket -- by one 1024-thread workgroup per vertex with a table in a global
-// memory pool.  Pruning flags are kept as per-vertex stamps; a vertex whose
-// stamp is raised to the next iteration's value is appended to that
-// iteration's queue (wave-aggregated atomics per bucket).
+// memory pool.  Pruning flags are per-vertex stamps: a mover writes the next
+// iteration's stamp into its neighbours' slots, and the next queue is built
+// by an ordered compaction of the stamped vertices (lv_bucket.h).
+#include <algorithm>
+
+#include "lv_bucket.h"
 #include "lv_internal.h"
 
 namespace lv {
@@ -48,18 +51,7 @@ void dispatch_types(const LevelTypes& t, Fn&& fn) {
     else wk(TypeTag<int32_t>{});
 }
 
-// Count lanes per bucket with one atomic per bucket per wave.
-__device__ __forceinline__ void wave_count(bool want, int b, int32_t* count) {
-    const int lane = __lane_id();
-    u64 pending = __ballot(want);
-    while (pending) {
-        int leader = __ffsll((long long)pending) - 1;
-        int lb = __shfl(b, leader);
-        u64 same = __ballot(want && b == lb);
-        if (lane == leader) atomicAdd(&count[lb], __popcll(same));
-        pending &= ~same;
-    }
-}
+inline unsigned blocks_for(int64_t items, int per_block) { return (unsigned)((items + per_block - 1) / per_block); }
 
 // Wave-aggregated append of (x, y) pairs to a flat array.
 __device__ __forceinline__ void wave_append_pair(bool want, int32_t x, int32_t y, int32_t* out, int32_t* count) {
@@ -81,19 +73,20 @@ __device__ __forceinline__ void wave_append_pair(bool want, int32_t x, int32_t y
 // Reductions over a group of G lanes; for G > 64 the group is the whole
 // workgroup and the cross-wave step goes through LDS.
 template <int G, typename KeyT>
-__device__ __forceinline__ void reduce_best(KeyT& key, int32_t& d, KeyT* s_k, int32_t* s_d) {
+__device__ __forceinline__ void reduce_best(KeyT& key, int32_t& d, i64& v, KeyT* s_k, int32_t* s_d, i64* s_v) {
     constexpr int GW = G < WAVE ? G : WAVE;
-    if constexpr (sizeof(KeyT) == 8) group_best64<GW>(*(i64*)&key, d);
-    else group_best128<GW>(*(i128*)&key, d);
+    if constexpr (sizeof(KeyT) == 8) group_best64<GW>(*(i64*)&key, d, v);
+    else group_best128<GW>(*(i128*)&key, d, v);
     if constexpr (G > WAVE) {
         const int w = threadIdx.x / WAVE;
-        if (threadIdx.x % WAVE == 0) { s_k[w] = key; s_d[w] = d; }
+        if (threadIdx.x % WAVE == 0) { s_k[w] = key; s_d[w] = d; s_v[w] = v; }
         __syncthreads();
         key = s_k[0];
         d = s_d[0];
+        v = s_v[0];
 #pragma unroll
         for (int k = 1; k < G / WAVE; k++)
-            if (better(s_k[k], s_d[k], key, d)) { key = s_k[k]; d = s_d[k]; }
+            if (better(s_k[k], s_d[k], key, d)) { key = s_k[k]; d = s_d[k]; v = s_v[k]; }
         __syncthreads();
     }
 }
@@ -127,36 +120,50 @@ __device__ __forceinline__ i64 reduce_max(i64 v, i64* s_t) {
     }
     return v;
 }
+// Broadcast lane 0's value to the group.
+template <int G>
+__device__ __forceinline__ int32_t group_bcast(int32_t v, int32_t* s_x) {
+    if constexpr (G <= WAVE) {
+        return __shfl(v, 0, G);
+    } else {
+        if (threadIdx.x == 0) s_x[0] = v;
+        __syncthreads();
+        v = s_x[0];
+        __syncthreads();
+        return v;
+    }
+}
 
 // ------------------------------------------------------------ pass init
 template <typename OffT>
 __global__ void __launch_bounds__(256) k_classify(const OffT* __restrict__ off, int64_t n, Buckets B,
                                                   uint8_t* __restrict__ vbucket, int32_t* __restrict__ Cp,
-                                                  i64* __restrict__ K, i64* __restrict__ Sig, Ctl* ctl) {
+                                                  i64* __restrict__ K, i64* __restrict__ Sig) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
     int b = 255;
-    if (v < n) {
-        const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-        if (deg > 0) {
-            b = B.nb;
-            for (int k = 0; k < B.nb; k++)
-                if (deg <= B.maxdeg[k]) { b = k; break; }
-        }
-        vbucket[v] = (uint8_t)b;
-        Cp[v] = (int32_t)v;
-        K[v] = 0;
-        Sig[v] = 0;
+    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+    if (deg > 0) {
+        b = B.nb;
+        for (int k = 0; k < B.nb; k++)
+            if (deg <= B.maxdeg[k]) { b = k; break; }
     }
-    wave_count(v < n && b != 255, b, ctl->bcount);
+    vbucket[v] = (uint8_t)b;
+    Cp[v] = (int32_t)v;
+    K[v] = 0;
+    Sig[v] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_fill_buckets(int64_t n, const uint8_t* __restrict__ vbucket,
-                                                      int32_t* __restrict__ blist, const int64_t* __restrict__ seg,
-                                                      Ctl* ctl) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = v < n ? vbucket[v] : 255;
-    wave_enqueue(b != 255, b, (int32_t)v, blist, seg, ctl->bcursor);
-}
+struct VBucket {
+    const uint8_t* vb;
+    __device__ __forceinline__ int operator()(int64_t v) const { return vb[v]; }
+};
+struct MarkBucket {
+    const uint8_t* vb;
+    const uint32_t* mark;
+    uint32_t stamp;
+    __device__ __forceinline__ int operator()(int64_t v) const { return mark[v] == stamp ? (int)vb[v] : 255; }
+};
 
 // K'[i] = sum of i's arc weights (self-loop once); Sigma'[i] = K'[i].
 template <typename OffT, int WK, int G>
@@ -166,10 +173,13 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_rowsum(Graph<OffT, WK> g,
     constexpr int BLOCK = G > 256 ? G : 256;
     constexpr int NG = BLOCK / G;
     __shared__ i64 s_t[BLOCK / WAVE];
+    __shared__ u64 s_max;
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t slot = (int64_t)blockIdx.x * NG + grp;
     const bool active = slot < count;
     const int32_t i = active ? list[slot] : 0;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
     i64 s = 0;
     if (active)
         for (i64 e = (i64)g.off[i] + lane; e < (i64)g.off[i + 1]; e += G) s += g.weight(e);
@@ -177,15 +187,17 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_rowsum(Graph<OffT, WK> g,
     if (active && lane == 0) {
         K[i] = s;
         Sig[i] = s;
-        atomicMax(&ctl->kmax, (u64)s);
+        atomicMax(&s_max, (u64)s);
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max) atomicMax(&ctl->kmax, s_max);
 }
 
-// Table capacity of a hub: next power of two >= 2 * (bound on distinct
-// neighbour communities) = 2 * min(degree, n).
+// Static position of each hub and its table capacity: next power of two >=
+// 2 * (bound on distinct neighbour communities) = 2 * min(degree, n).
 template <typename OffT>
 __global__ void k_hub_caps(const OffT* __restrict__ off, int64_t n, const int32_t* __restrict__ list, int32_t count,
-                           int64_t* __restrict__ caps) {
+                           int64_t* __restrict__ caps, int32_t* __restrict__ hubpos) {
     const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= count) return;
     const int32_t v = list[h];
@@ -194,47 +206,120 @@ __global__ void k_hub_caps(const OffT* __restrict__ off, int64_t n, const int32_
     uint64_t cap = 1;
     while (cap < want) cap <<= 1;
     caps[h] = (int64_t)cap;
+    hubpos[v] = (int32_t)h;
 }
 
 // ------------------------------------------------------------ local moving
+// Modes: SYNC decides against the iteration's snapshot and records moves;
+// ASYNC_CACHED applies moves in place with ordinary (XCD-L2 cached) loads;
+// ASYNC_COHERENT does the same with device-scope loads and stores of C' and
+// Sigma', so moves made on other chiplets are seen within the launch.
+enum { M_SYNC = 0, M_ASYNC_CACHED = 1, M_ASYNC_COHERENT = 2 };
+
+template <int MODE>
+__device__ __forceinline__ int32_t ld_c(const int32_t* p) {
+    if constexpr (MODE == M_ASYNC_COHERENT) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <int MODE>
+__device__ __forceinline__ i64 ld_s(const i64* p) {
+    if constexpr (MODE == M_ASYNC_COHERENT) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <int MODE>
+__device__ __forceinline__ void st_c(int32_t* p, int32_t v) {
+    if constexpr (MODE == M_ASYNC_COHERENT) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
+struct Decision {
+    int32_t target;  // -1: stay
+    i64 kid;         // K_{i->target}
+    i64 kic;         // K_{i->c}
+    i128 gain;       // gain against the state read
+    i64 nd;          // distinct neighbour communities
+};
+
 // Per-group decision after the table is filled.  Scans the table slots owned
-// by this lane, reduces over the group and returns the move target (or -1)
-// with its gain in *gain_out; writes the group's distinct-community count.
-template <int G, typename KeyT, typename AccT>
-__device__ __forceinline__ int32_t decide(const MoveArgs& a, const int32_t* keys, const AccT* vals, int64_t cap,
-                                          int lane, bool active, int32_t i, int32_t c, i64 Ki, KeyT* s_k,
-                                          int32_t* s_d, i64* s_t, i128* gain_out, i64* nd_out) {
+// by this lane, reduces over the group; every lane returns the same result.
+template <int G, int MODE, typename KeyT, typename AccT>
+__device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* keys, const AccT* vals, int64_t cap,
+                                           int lane, bool active, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
+                                           i64* s_v, i64* s_t) {
     KeyT bk = 0;
     int32_t bd = EMPTY_KEY;
-    i64 kic = 0, nd = 0;
+    i64 bv = 0, kic = 0, nd = 0;
     for (int64_t s = lane; s < cap; s += G) {
         const int32_t d = keys[s];
         if (d == EMPTY_KEY) continue;
         ++nd;
         const i64 v = (i64)vals[s];
         if (d == c) { kic = v; continue; }
-        const KeyT key = (KeyT)a.W * v - (KeyT)Ki * a.Sig[d];
-        if (bd == EMPTY_KEY || better(key, d, bk, bd)) { bk = key; bd = d; }
+        const KeyT key = (KeyT)a.W * v - (KeyT)Ki * ld_s<MODE>(&a.Sig[d]);
+        if (bd == EMPTY_KEY || better(key, d, bk, bd)) { bk = key; bd = d; bv = v; }
     }
     // Lanes without a candidate must not win: give them the smallest key.
     if (bd == EMPTY_KEY) bk = (sizeof(KeyT) == 8) ? (KeyT)INT64_MIN : (KeyT)(((i128)1) << 127);
-    reduce_best<G, KeyT>(bk, bd, s_k, s_d);
+    reduce_best<G, KeyT>(bk, bd, bv, s_k, s_d, s_v);
     kic = reduce_max<G>(kic, s_t);
-    *nd_out = reduce_sum<G>(nd, s_t);
-    int32_t target = -1;
-    i128 gain = 0;
+    Decision r{-1, 0, kic, 0, reduce_sum<G>(nd, s_t)};
     if (active && bd != EMPTY_KEY) {
-        const i64 Sc = a.Sig[c];
+        const i64 Sc = ld_s<MODE>(&a.Sig[c]);
         const KeyT stay = (KeyT)a.W * kic - (KeyT)Ki * (Sc - Ki);
         const KeyT gk = bk - stay;
-        if (gk > 0 && (!a.pl || bd < c)) { target = bd; gain = (i128)gk; }
+        if (gk > 0 && (!a.pl || bd < c)) { r.target = bd; r.kid = bv; r.gain = (i128)gk; }
     }
-    *gain_out = gain;
-    (void)i;
-    return target;
+    return r;
 }
 
-template <typename OffT, int WK, typename AccT, int G, int CAP, bool SYNC>
+// ASYNC move with validation: Sigma of the target is updated by an atomic
+// add whose return value is the exact total before this vertex joins; the
+// gain is recomputed from that value and the current Sigma_c, and the move is
+// undone if it is no longer positive.  Concurrent joins of one community are
+// therefore each checked against the community as it really is.
+template <int MODE>
+__device__ __forceinline__ bool apply_async(const MoveArgs& a, int32_t i, int32_t c, i64 Ki, Decision& dcs) {
+    const i64 old_d = (i64)atomicAdd((u64*)&a.Sig[dcs.target], (u64)Ki);
+    const i64 Sc = ld_s<MODE>(&a.Sig[c]);
+    const i128 g = (i128)a.W * (dcs.kid - dcs.kic) - (i128)Ki * ((i128)old_d - Sc + Ki);
+    if (g > 0) {
+        atomicAdd((u64*)&a.Sig[c], (u64)(-Ki));
+        st_c<MODE>(&a.Cp[i], dcs.target);
+        dcs.gain = g;
+        return true;
+    }
+    atomicAdd((u64*)&a.Sig[dcs.target], (u64)(-Ki));
+    dcs.target = -1;
+    dcs.gain = 0;
+    return false;
+}
+
+// Stamp the neighbours of mover i for the next iteration's queue.
+template <int G, typename OffT, int WK>
+__device__ __forceinline__ void mark_neighbours(const MoveArgs& a, const Graph<OffT, WK>& g, int32_t i, i64 o0,
+                                                i64 o1, int lane) {
+    for (i64 e = o0 + lane; e < o1; e += G) {
+        const int32_t j = g.idx[e];
+        if (j != i && a.mark[j] != a.stamp_next) a.mark[j] = a.stamp_next;
+    }
+}
+
+__device__ __forceinline__ void add_block_totals(Ctl* ctl, int bucket, u64 ne, u64 na, u64 nd, u64 nm, u64 nma,
+                                                 i128 gain) {
+    const int st = blockIdx.x & (STRIPES - 1);
+    if (!ne) return;
+    atomicAdd(&ctl->bstat[0][bucket][st], ne);
+    atomicAdd(&ctl->bstat[1][bucket][st], na);
+    atomicAdd(&ctl->bstat[2][bucket][st], nd);
+    if (nm) {
+        atomic_add_i128(&ctl->s_lo[st], &ctl->s_hi[st], gain);
+        atomicAdd(&ctl->moves[st], nm);
+        atomicAdd(&ctl->bstat[3][bucket][st], nm);
+        atomicAdd(&ctl->bstat[4][bucket][st], nma);
+    }
+}
+
+template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE>
 __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, const int32_t* __restrict__ list,
                                                                 int32_t count) {
     constexpr int BLOCK = G > 256 ? G : 256;
@@ -245,7 +330,9 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
     __shared__ i128 s_k128[BLOCK / WAVE];
     __shared__ i64 s_k64[BLOCK / WAVE];
     __shared__ int32_t s_d[BLOCK / WAVE];
+    __shared__ i64 s_v[BLOCK / WAVE];
     __shared__ i64 s_t[BLOCK / WAVE];
+    __shared__ int32_t s_x[1];
     __shared__ i128 s_gain[NG];
     __shared__ int32_t s_dec[NG];
     __shared__ i64 s_arcs[NG], s_nd[NG];
@@ -263,7 +350,7 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
     int32_t c = 0;
     i64 Ki = 0, o0 = 0, o1 = 0;
     if (active) {
-        c = a.Cp[i];
+        c = ld_c<MODE>(&a.Cp[i]);
         Ki = a.K[i];
         o0 = (i64)g.off[i];
         o1 = (i64)g.off[i + 1];
@@ -271,45 +358,28 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
     for (i64 e = o0 + lane; e < o1; e += G) {
         const int32_t j = g.idx[e];
         if (j == i) continue;
-        const int32_t d = a.Cp[j];
+        const int32_t d = ld_c<MODE>(&a.Cp[j]);
         table_add<AccT>(keys, vals, CAP - 1, hash_slot<L2C>(d), d, (AccT)g.weight(e));
     }
     group_sync<G>();
 
-    i128 gain;
-    i64 nd;
-    int32_t target;
-    if (!a.wide)
-        target = decide<G, i64, AccT>(a, keys, vals, CAP, lane, active, i, c, Ki, s_k64, s_d, s_t, &gain, &nd);
-    else
-        target = decide<G, i128, AccT>(a, keys, vals, CAP, lane, active, i, c, Ki, s_k128, s_d, s_t, &gain, &nd);
+    Decision dcs = !a.wide
+        ? decide<G, MODE, i64, AccT>(a, keys, vals, CAP, lane, active, c, Ki, s_k64, s_d, s_v, s_t)
+        : decide<G, MODE, i128, AccT>(a, keys, vals, CAP, lane, active, c, Ki, s_k128, s_d, s_v, s_t);
 
-    if (lane == 0) {
-        s_gain[grp] = gain;
-        s_dec[grp] = target;
-        s_arcs[grp] = active ? (o1 - o0) : -1;
-        s_nd[grp] = nd;
-    }
-    if constexpr (SYNC) {
-        wave_append_pair(lane == 0 && target >= 0, i, target, a.movers, &a.ctl->movers);
+    if constexpr (MODE == M_SYNC) {
+        wave_append_pair(lane == 0 && dcs.target >= 0, i, dcs.target, a.movers, &a.ctl->movers);
     } else {
-        if (lane == 0 && target >= 0) {
-            atomicAdd((u64*)&a.Sig[c], (u64)(-Ki));
-            atomicAdd((u64*)&a.Sig[target], (u64)Ki);
-            a.Cp[i] = target;
-        }
-        if (a.prune && target >= 0) {
-            for (i64 e = o0 + lane; e < o1; e += G) {
-                const int32_t j = g.idx[e];
-                bool want = false;
-                int b = 0;
-                if (j != i && a.mark[j] != a.stamp_next) {
-                    b = a.vbucket[j];
-                    want = b != 255 && atomicExch(&a.mark[j], a.stamp_next) != a.stamp_next;
-                }
-                wave_enqueue(want, b, j, a.qnext, a.qseg, a.ctl->qcount);
-            }
-        }
+        int32_t t = -1;
+        if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, i, c, Ki, dcs)) t = dcs.target;
+        t = group_bcast<G>(t, s_x);
+        if (a.prune && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
+    }
+    if (lane == 0) {
+        s_gain[grp] = dcs.gain;
+        s_dec[grp] = dcs.target;
+        s_arcs[grp] = active ? (o1 - o0) : -1;
+        s_nd[grp] = dcs.nd;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -322,102 +392,69 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
             ndt += (u64)s_nd[k];
             if (s_dec[k] >= 0) { sg += s_gain[k]; nm++; nma += (u64)s_arcs[k]; }
         }
-        if (ne) {
-            const int b = a.bucket;
-            atomicAdd(&a.ctl->b_eval[b], ne);
-            atomicAdd(&a.ctl->b_arcs[b], na);
-            atomicAdd(&a.ctl->b_distinct[b], ndt);
-            if (nm) {
-                atomic_add_i128(&a.ctl->s_lo, &a.ctl->s_hi, sg);
-                atomicAdd(&a.ctl->moves, nm);
-                atomicAdd(&a.ctl->b_moves[b], nm);
-                atomicAdd(&a.ctl->b_marcs[b], nma);
-            }
-        }
+        add_block_totals(a.ctl, a.bucket, ne, na, ndt, nm, nma, sg);
     }
 }
 
-// Hub path: one 1024-thread workgroup per vertex, table in a global pool.
-template <typename OffT, int WK, typename AccT, bool SYNC>
+// Hub path: one 1024-thread workgroup per queued hub, table in a global pool
+// at the hub's static position; hubs outside this launch's chunk exit.
+template <typename OffT, int WK, typename AccT, int MODE>
 __global__ void __launch_bounds__(HUB_G) k_move_hub(MoveArgs a, const int32_t* __restrict__ list, int32_t count) {
     constexpr int G = HUB_G;
     __shared__ i128 s_k128[G / WAVE];
     __shared__ i64 s_k64[G / WAVE];
     __shared__ int32_t s_d[G / WAVE];
+    __shared__ i64 s_v[G / WAVE];
     __shared__ i64 s_t[G / WAVE];
+    __shared__ int32_t s_x[1];
     const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
     const int64_t slot = blockIdx.x;
     if (slot >= count) return;
     const int32_t i = list[slot];
-    if (a.check_mark && a.mark[i] != a.stamp_cur) return;  // not queued this iteration (uniform per block)
+    const int32_t pos = a.hubpos[i];
+    if (pos < a.chunk_lo || pos >= a.chunk_hi) return;  // uniform per block
     const int lane = threadIdx.x;
-    const int64_t toff = a.hub_off[slot] - a.hub_base;
-    const int64_t cap = a.hub_off[slot + 1] - a.hub_off[slot];
+    const int64_t toff = a.hub_pre[pos] - a.hub_pre[a.chunk_lo];
+    const int64_t cap = a.hub_pre[pos + 1] - a.hub_pre[pos];
     const int log2cap = __ffsll((long long)cap) - 1;
     int32_t* keys = a.hub_keys + toff;
     AccT* vals = (AccT*)a.hub_vals + toff;
     for (int64_t s = lane; s < cap; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }
     __syncthreads();
-    const int32_t c = a.Cp[i];
+    const int32_t c = ld_c<MODE>(&a.Cp[i]);
     const i64 Ki = a.K[i];
     const i64 o0 = (i64)g.off[i], o1 = (i64)g.off[i + 1];
     for (i64 e = o0 + lane; e < o1; e += G) {
         const int32_t j = g.idx[e];
         if (j == i) continue;
-        const int32_t d = a.Cp[j];
+        const int32_t d = ld_c<MODE>(&a.Cp[j]);
         table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d, (AccT)g.weight(e));
     }
     __syncthreads();
-    i128 gain;
-    i64 nd;
-    int32_t target;
-    if (!a.wide)
-        target = decide<G, i64, AccT>(a, keys, vals, cap, lane, true, i, c, Ki, s_k64, s_d, s_t, &gain, &nd);
-    else
-        target = decide<G, i128, AccT>(a, keys, vals, cap, lane, true, i, c, Ki, s_k128, s_d, s_t, &gain, &nd);
-    if constexpr (SYNC) {
-        wave_append_pair(lane == 0 && target >= 0, i, target, a.movers, &a.ctl->movers);
+    Decision dcs = !a.wide
+        ? decide<G, MODE, i64, AccT>(a, keys, vals, cap, lane, true, c, Ki, s_k64, s_d, s_v, s_t)
+        : decide<G, MODE, i128, AccT>(a, keys, vals, cap, lane, true, c, Ki, s_k128, s_d, s_v, s_t);
+    if constexpr (MODE == M_SYNC) {
+        wave_append_pair(lane == 0 && dcs.target >= 0, i, dcs.target, a.movers, &a.ctl->movers);
     } else {
-        if (lane == 0 && target >= 0) {
-            atomicAdd((u64*)&a.Sig[c], (u64)(-Ki));
-            atomicAdd((u64*)&a.Sig[target], (u64)Ki);
-            a.Cp[i] = target;
-        }
-        if (a.prune && target >= 0) {
-            for (i64 e = o0 + lane; e < o1; e += G) {
-                const int32_t j = g.idx[e];
-                bool want = false;
-                int b = 0;
-                if (j != i && a.mark[j] != a.stamp_next) {
-                    b = a.vbucket[j];
-                    want = b != 255 && atomicExch(&a.mark[j], a.stamp_next) != a.stamp_next;
-                }
-                wave_enqueue(want, b, j, a.qnext, a.qseg, a.ctl->qcount);
-            }
-        }
+        int32_t t = -1;
+        if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, i, c, Ki, dcs)) t = dcs.target;
+        t = group_bcast<G>(t, s_x);
+        if (a.prune && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
     }
-    if (lane == 0) {
-        const int b = a.bucket;
-        atomicAdd(&a.ctl->b_eval[b], 1ull);
-        atomicAdd(&a.ctl->b_arcs[b], (u64)(o1 - o0));
-        atomicAdd(&a.ctl->b_distinct[b], (u64)nd);
-        if (target >= 0) {
-            atomic_add_i128(&a.ctl->s_lo, &a.ctl->s_hi, gain);
-            atomicAdd(&a.ctl->moves, 1ull);
-            atomicAdd(&a.ctl->b_moves[b], 1ull);
-            atomicAdd(&a.ctl->b_marcs[b], (u64)(o1 - o0));
-        }
-    }
+    if (lane == 0)
+        add_block_totals(a.ctl, a.bucket, 1, (u64)(o1 - o0), (u64)dcs.nd, dcs.target >= 0 ? 1 : 0,
+                         dcs.target >= 0 ? (u64)(o1 - o0) : 0, dcs.gain);
 }
 
-// SYNC: apply the recorded decisions together, then flag the movers'
+// SYNC: apply the recorded decisions together, then stamp the movers'
 // neighbours for the next iteration.  One wave per mover.
 template <typename OffT>
 __global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a) {
     const int32_t nm = *(volatile int32_t*)&a.ctl->movers;
     const int lane = threadIdx.x % WAVE;
     const int64_t nw = (int64_t)gridDim.x * (256 / WAVE);
-    const OffT* off = (const OffT*)a.off;
+    const Graph<OffT, 0> g{(const OffT*)a.off, a.idx, nullptr};
     for (int64_t m = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE; m < nm; m += nw) {
         const int32_t i = a.movers[2 * m], d = a.movers[2 * m + 1];
         if (lane == 0) {
@@ -427,41 +464,42 @@ __global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a) {
             atomicAdd((u64*)&a.Sig[d], (u64)Ki);
             a.Cp[i] = d;
         }
-        if (a.prune) {
-            const i64 o0 = (i64)off[i], o1 = (i64)off[i + 1];
-            for (i64 e = o0 + lane; e < o1; e += WAVE) {
-                const int32_t j = a.idx[e];
-                bool want = false;
-                int b = 0;
-                if (j != i && a.mark[j] != a.stamp_next) {
-                    b = a.vbucket[j];
-                    want = b != 255 && atomicExch(&a.mark[j], a.stamp_next) != a.stamp_next;
-                }
-                wave_enqueue(want, b, j, a.qnext, a.qseg, a.ctl->qcount);
-            }
-        }
+        if (a.prune) mark_neighbours<WAVE>(a, g, i, (i64)g.off[i], (i64)g.off[i + 1], lane);
     }
 }
-
-inline unsigned blocks_for(int64_t items, int per_block) { return (unsigned)((items + per_block - 1) / per_block); }
 
 }  // namespace
 
 void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int32_t* Cp, i64* K, i64* Sig,
-                     Ctl* ctl, hipStream_t s) {
+                     hipStream_t s) {
     if (L.n <= 0) return;
     if (L.t.off64)
-        k_classify<int64_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, B, vbucket, Cp, K,
-                                                                  Sig, ctl);
+        k_classify<int64_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, B, vbucket, Cp, K, Sig);
     else
-        k_classify<int32_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, B, vbucket, Cp, K,
-                                                                  Sig, ctl);
+        k_classify<int32_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, B, vbucket, Cp, K, Sig);
 }
 
-void launch_fill_buckets(int64_t n, const uint8_t* vbucket, int32_t* blist, const int64_t* seg, Ctl* ctl,
-                         hipStream_t s) {
-    if (n <= 0) return;
-    k_fill_buckets<<<blocks_for(n, 256), 256, 0, s>>>(n, vbucket, blist, seg, ctl);
+void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint32_t* mark, uint32_t stamp, int use_mark,
+                        int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
+                        hipStream_t s) {
+    constexpr int NB = NB_MOVE + 1;
+    const int64_t nb = bucket_blocks(n);
+    if (n <= 0) {
+        hipMemsetAsync(totals, 0, NB * sizeof(int32_t), s);
+        return;
+    }
+    if (use_mark) {
+        MarkBucket bf{vbucket, mark, stamp};
+        k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb);
+        scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
+        k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out);
+    } else {
+        VBucket bf{vbucket};
+        k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb);
+        scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
+        k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out);
+    }
+    k_bucket_totals<<<1, 32, 0, s>>>(blkoff, nb, NB, totals);
 }
 
 void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t count, i64* K, i64* Sig, Ctl* ctl,
@@ -488,15 +526,18 @@ void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t 
     });
 }
 
-void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, hipStream_t s) {
+void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, int32_t* hubpos,
+                     hipStream_t s) {
     if (count <= 0) return;
     if (L.t.off64)
-        k_hub_caps<int64_t><<<blocks_for(count, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, list, count, caps);
+        k_hub_caps<int64_t><<<blocks_for(count, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, list, count, caps,
+                                                                    hubpos);
     else
-        k_hub_caps<int32_t><<<blocks_for(count, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, list, count, caps);
+        k_hub_caps<int32_t><<<blocks_for(count, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, list, count, caps,
+                                                                    hubpos);
 }
 
-void launch_move(const LevelView& L, int bucket, int sync, const MoveArgs& a, const int32_t* list, int32_t count,
+void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
                  hipStream_t s) {
     if (count <= 0) return;
     dispatch_types(L.t, [&](auto o, auto w, auto ac) {
@@ -508,8 +549,10 @@ void launch_move(const LevelView& L, int bucket, int sync, const MoveArgs& a, co
             constexpr int G = MOVE_G[b], CAP = MOVE_CAP[b];
             constexpr int BLOCK = G > 256 ? G : 256;
             const unsigned grid = blocks_for(count, BLOCK / G);
-            if (sync) k_move_lds<OffT, WK, AccT, G, CAP, true><<<grid, BLOCK, 0, s>>>(a, list, count);
-            else k_move_lds<OffT, WK, AccT, G, CAP, false><<<grid, BLOCK, 0, s>>>(a, list, count);
+            if (mode == M_SYNC) k_move_lds<OffT, WK, AccT, G, CAP, M_SYNC><<<grid, BLOCK, 0, s>>>(a, list, count);
+            else if (mode == M_ASYNC_CACHED)
+                k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_CACHED><<<grid, BLOCK, 0, s>>>(a, list, count);
+            else k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_COHERENT><<<grid, BLOCK, 0, s>>>(a, list, count);
         };
         switch (bucket) {
             case 0: go(IntTag<0>{}); break;
@@ -521,15 +564,17 @@ void launch_move(const LevelView& L, int bucket, int sync, const MoveArgs& a, co
     });
 }
 
-void launch_move_hub(const LevelView& L, int sync, const MoveArgs& a, const int32_t* list, int32_t count,
+void launch_move_hub(const LevelView& L, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
                      hipStream_t s) {
     if (count <= 0) return;
     dispatch_types(L.t, [&](auto o, auto w, auto ac) {
         using OffT = typename decltype(o)::type;
         constexpr int WK = decltype(w)::value;
         using AccT = typename decltype(ac)::type;
-        if (sync) k_move_hub<OffT, WK, AccT, true><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
-        else k_move_hub<OffT, WK, AccT, false><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
+        if (mode == M_SYNC) k_move_hub<OffT, WK, AccT, M_SYNC><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
+        else if (mode == M_ASYNC_CACHED)
+            k_move_hub<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
+        else k_move_hub<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
     });
 }
 
