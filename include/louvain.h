@@ -58,6 +58,7 @@ typedef enum { LOUVAIN_ASYNC = 0, LOUVAIN_SYNC = 1 } louvain_mode;
  *   again only after a neighbour changed community. */
 typedef enum { LOUVAIN_PRUNE_NONE = 0, LOUVAIN_PRUNE_FLAGS = 1 } louvain_pruner;
 
+
 /* Input graph.  offsets: device, n+1 entries of int32 (offset_bits = 32) or
  * int64 (offset_bits = 64), offsets[0] = 0, non-decreasing, offsets[n] = nnz.
  * indices: device, nnz int32 in [0, n).  weights: device, nnz int32 > 0, or

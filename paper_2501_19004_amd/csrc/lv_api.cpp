@@ -43,7 +43,7 @@ struct Layout {
     size_t ctl, seg, C, Cp, K, Sig, mark, vbucket, blist, qa, qb, movers, hcaps, hpre;
     size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
     size_t hidx, hw, sup_off[2], sup_idx[2], sup_w[2], pool_keys, pool_vals, scan;
-    size_t md, mpos, bnch, bchpre, bitmaps, hubpos, blkcnt, blkoff;
+    size_t md, mpos, bnch, bchpre, bitmaps, gdec, blkcnt, blkoff;
     int64_t bitmap_words;
     int64_t pool_entries;
     size_t total;
@@ -92,7 +92,7 @@ bool make_layout(int64_t n, int64_t m, Layout* L) {
     L->pool_keys = take((size_t)pool * 4);
     L->pool_vals = take((size_t)pool * 8);
     L->scan = take(scan_scratch_bytes(n + 2));
-    L->hubpos = take(N * 4);
+    L->gdec = take(N * 4);
     L->blkcnt = take((size_t)(MAX_BUCKETS * (bucket_blocks(n + 1) + 1) + 8) * 4);
     L->blkoff = take((size_t)(MAX_BUCKETS * (bucket_blocks(n + 1) + 1) + 8) * 4);
     L->md = take((N + 1) * 8);
@@ -111,12 +111,14 @@ struct KRec {
     int64_t bytes;
 };
 
-enum KName { K_MOVE0 = 0, K_MOVE1, K_MOVE2, K_MOVE3, K_MOVE4, K_MOVE_HUB, K_SYNC_APPLY, K_PASS_INIT, K_AGG_PREP,
-             K_AGG0, K_AGG1, K_AGG2, K_AGG3, K_AGG_BIG_INSERT, K_AGG_BIG_EXTRACT, K_COMPACT, K_QUEUE, K_COUNT };
-const char* KNAMES[K_COUNT] = {"move_b0", "move_b1", "move_b2", "move_b3", "move_b4", "move_hub", "sync_apply",
+enum KName { K_MOVE_FUSED = 0, K_MOVE1, K_MOVE2, K_MOVE3, K_MOVE4, K_MOVE_HUB, K_SYNC_APPLY, K_PASS_INIT, K_AGG_PREP,
+             K_AGG0, K_AGG1, K_AGG2, K_AGG3, K_AGG_BIG_INSERT, K_AGG_BIG_EXTRACT, K_COMPACT, K_QUEUE, K_HUB_MARK,
+             K_COUNT };
+const char* KNAMES[K_COUNT] = {"move_b0_3", "move_unused1", "move_unused2", "move_unused3", "move_b4", "move_hub",
+                               "sync_apply",
                                "pass_init", "aggregate_prep", "aggregate_b0", "aggregate_b1", "aggregate_b2",
                                "aggregate_b3", "aggregate_big_insert", "aggregate_big_extract", "compact",
-                               "queue_build"};
+                               "queue_build", "hub_mark"};
 
 }  // namespace
 
@@ -446,7 +448,7 @@ louvain_status Runner::run() {
     uint8_t* vb = at<uint8_t>(Y.vbucket);
     int32_t* blist = at<int32_t>(Y.blist);
     int32_t* qbuf[2] = {at<int32_t>(Y.qa), at<int32_t>(Y.qb)};
-    int32_t* hubpos = at<int32_t>(Y.hubpos);
+    int32_t* gdec = at<int32_t>(Y.gdec);
     int32_t* blkcnt = at<int32_t>(Y.blkcnt);
     int32_t* blkoff = at<int32_t>(Y.blkoff);
     void* scan = at<void>(Y.scan);
@@ -485,17 +487,26 @@ louvain_status Runner::run() {
             for (int b = 0; b < NBT; b++)
                 launch_rowsum(L, b, blist + segs[b], bcount[b], K, Sig, ctl(), s);
         });
-        // hub tables: static positions in ascending vertex order
+        // hub tables and insert chunks over the static hub list (ascending vertex id)
         const int32_t nhub = bcount[NB_MOVE];
+        const int32_t* hub_list = blist + segs[NB_MOVE];
         int64_t* hpre = at<int64_t>(Y.hpre);
-        std::vector<std::pair<int32_t, int32_t>> hub_chunks;
+        int64_t* hchpre = at<int64_t>(Y.bchpre);
+        std::vector<int64_t> hch_pre;
+        std::vector<std::pair<int32_t, int32_t>> hub_groups;
         if (nhub > 0) {
-            launch_hub_caps(L, blist + segs[NB_MOVE], nhub, at<int64_t>(Y.hcaps), hubpos, s);
+            launch_hub_caps(L, hub_list, nhub, at<int64_t>(Y.hcaps), at<int64_t>(Y.bnch), s);
             scan_i64_to_i64(at<int64_t>(Y.hcaps), hpre, nhub, scan, s);
+            scan_i64_to_i64(at<int64_t>(Y.bnch), hchpre, nhub, scan, s);
             hub_pre.resize(nhub + 1);
+            hch_pre.resize(nhub + 1);
             if ((st = readback(H, hub_pre.data(), hpre, (nhub + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
-            if (!chunks(hub_pre, Y.pool_entries, &hub_chunks))
+            if ((st = readback(H, hch_pre.data(), hchpre, (nhub + 1) * sizeof(int64_t))) != LOUVAIN_OK) return st;
+            if (!chunks(hub_pre, Y.pool_entries, &hub_groups))
                 return fail(H, LOUVAIN_ERR_WORKSPACE, "hub hash table exceeds the workspace pool");
+            int64_t most = 0;
+            for (auto& gr : hub_groups) most = std::max(most, hub_pre[gr.second] - hub_pre[gr.first]);
+            launch_big_clear(at<int32_t>(Y.pool_keys), at<void>(Y.pool_vals), most, s);
         }
         u64 kmax = 0;
         if ((st = readback(H, &kmax, &ctl()->kmax, sizeof(u64))) != LOUVAIN_OK) return st;
@@ -533,39 +544,70 @@ louvain_status Runner::run() {
             a.mark = mark;
             a.ctl = ctl();
             a.movers = at<int32_t>(Y.movers);
-            a.hubpos = hubpos;
+            a.vbucket = vb;
+            a.hub_list = hub_list;
             a.hub_pre = hpre;
+            a.hch_pre = hchpre;
+            a.all_queued = (t == 0 || !prune) ? 1 : 0;
+            a.stamp_cur = stamp_next - 1;
+            a.gdec = gdec;
             a.hub_keys = at<int32_t>(Y.pool_keys);
             a.hub_vals = at<void>(Y.pool_vals);
-            // slice sl of a bucket segment: [cnt*sl/ns, cnt*(sl+1)/ns)
+            // hubs: chunked inserts, one decision per hub, chunked stamping, for
+            // the static hub positions [s_lo, s_hi) whose tables share the pool
+            const bool hubs_now = nhub > 0 && counts[NB_MOVE] > 0;
+            auto hubs_range = [&](int32_t s_lo, int32_t s_hi, bool decide_phase, bool mark_phase) {
+                a.bucket = NB_MOVE;
+                for (auto& gr : hub_groups) {
+                    const int32_t lo = std::max(gr.first, s_lo), hi = std::min(gr.second, s_hi);
+                    if (lo >= hi) continue;
+                    a.g_lo = lo;
+                    a.g_hi = hi;
+                    const int64_t nchunks = hch_pre[hi] - hch_pre[lo];
+                    if (decide_phase)
+                        timed(H, K_MOVE_HUB, 0, [&] {
+                            launch_hub_insert(LM, mode, a, nchunks, s);
+                            launch_hub_decide(LM, mode, a, s);
+                        });
+                    if (mark_phase && prune) timed(H, K_HUB_MARK, 0, [&] { launch_hub_mark(L, a, nchunks, s); });
+                }
+            };
+            // ASYNC: the iteration runs as ns slices in vertex-id order (each
+            // bucket's queue is sorted by id; slice sl takes the sl-th share of
+            // every bucket), at least ~32 queued vertices per slice.
+            int64_t queued = 0;
+            for (int b = 0; b < NBT; b++) queued += counts[b];
             const bool slice_now = P.async_slice_iters <= 0 || t < P.async_slice_iters;
-            const int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
+            int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
+            ns = (int)std::max<int64_t>(1, std::min<int64_t>(ns, queued / 32));
             for (int sl = 0; sl < ns; sl++) {
                 auto lo_of = [&](int b) { return (int32_t)((int64_t)counts[b] * sl / ns); };
                 auto hi_of = [&](int b) { return (int32_t)((int64_t)counts[b] * (sl + 1) / ns); };
-                auto run_hubs = [&] {
-                    const int32_t lo = lo_of(NB_MOVE), hi = hi_of(NB_MOVE);
-                    if (hi <= lo) return;
-                    a.bucket = NB_MOVE;
-                    for (auto& ch : hub_chunks) {
-                        a.chunk_lo = ch.first;
-                        a.chunk_hi = ch.second;
-                        timed(H, K_MOVE_HUB, 0,
-                              [&] { launch_move_hub(LM, mode, a, cur_list + csegs[NB_MOVE] + lo, hi - lo, s); });
-                    }
-                };
-                if (P.bucket_order) run_hubs();
-                for (int k = 0; k < NB_MOVE; k++) {
-                    const int b = P.bucket_order ? NB_MOVE - 1 - k : k;
+                const int32_t h_lo = (int32_t)((int64_t)nhub * sl / ns), h_hi = (int32_t)((int64_t)nhub * (sl + 1) / ns);
+                if (P.bucket_order && hubs_now) hubs_range(h_lo, h_hi, true, !sync);
+                FusedLists f{};
+                f.blk_pre[0] = 0;
+                for (int b = 0; b < 4; b++) {
                     const int32_t lo = lo_of(b), hi = hi_of(b);
-                    if (hi <= lo) continue;
-                    a.bucket = b;
-                    timed(H, K_MOVE0 + b, 0,
-                          [&] { launch_move(LM, b, mode, a, cur_list + csegs[b] + lo, hi - lo, s); });
+                    f.list[b] = cur_list + csegs[b] + lo;
+                    f.count[b] = hi - lo;
+                    const int ng = 256 / MOVE_G[b];
+                    f.blk_pre[b + 1] = f.blk_pre[b] + (f.count[b] + ng - 1) / ng;
                 }
-                if (!P.bucket_order) run_hubs();
+                if (f.blk_pre[4] > 0) timed(H, K_MOVE_FUSED, 0, [&] { launch_move_fused(LM, mode, a, f, s); });
+                {
+                    const int32_t lo = lo_of(4), hi = hi_of(4);
+                    if (hi > lo) {
+                        a.bucket = 4;
+                        timed(H, K_MOVE4, 0, [&] { launch_move(LM, 4, mode, a, cur_list + csegs[4] + lo, hi - lo, s); });
+                    }
+                }
+                if (!P.bucket_order && hubs_now) hubs_range(h_lo, h_hi, true, !sync);
             }
-            if (sync) timed(H, K_SYNC_APPLY, 0, [&] { launch_sync_apply(L, a, s); });
+            if (sync) {
+                timed(H, K_SYNC_APPLY, 0, [&] { launch_sync_apply(L, a, s); });
+                if (hubs_now) hubs_range(0, nhub, false, true);
+            }
             if (prune)
                 timed(H, K_QUEUE, 0, [&] {
                     bucketize_vertices(n, vb, mark, stamp_next, 1, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
@@ -591,7 +633,7 @@ louvain_status Runner::run() {
                     if (de) {
                         const int64_t bytes = move_alg_bytes(LM, de, cur[1] - prev_b[1][b], cur[2] - prev_b[2][b],
                                                              cur[3] - prev_b[3][b], cur[4] - prev_b[4][b], sync);
-                        const int kind = b < NB_MOVE ? K_MOVE0 + b : K_MOVE_HUB;
+                        const int kind = b < 4 ? K_MOVE_FUSED : (b == 4 ? K_MOVE4 : K_MOVE_HUB);
                         for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
                             if (r->kind == kind) { r->bytes += bytes; break; }
                     }
@@ -852,7 +894,7 @@ louvain_status louvain_run(louvain_t* h) {
             h->kbytes[r2.kind] += r2.bytes;
         }
         double mv = 0, ag = 0;
-        for (int k = K_MOVE0; k <= K_SYNC_APPLY; k++) mv += h->kms[k];
+        for (int k = K_MOVE_FUSED; k <= K_SYNC_APPLY; k++) mv += h->kms[k];
         for (int k = K_AGG_PREP; k <= K_COMPACT; k++) ag += h->kms[k];
         h->st.ms_move = mv;
         h->st.ms_aggregate = ag;

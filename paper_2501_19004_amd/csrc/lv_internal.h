@@ -16,7 +16,8 @@ constexpr int NB_MOVE = 5;
 constexpr int MOVE_G[NB_MOVE] = {8, 16, 64, 256, 1024};
 constexpr int MOVE_CAP[NB_MOVE] = {16, 64, 256, 2048, 8192};
 constexpr int MOVE_DEFAULT_MAX[NB_MOVE] = {8, 32, 128, 1024, 4096};
-constexpr int HUB_G = 1024;
+constexpr int HUB_CH = 4096;    // arcs per hub insert chunk (one workgroup)
+constexpr int HUB_LCAP = 8192;  // LDS slots of a hub insert chunk
 
 // Aggregation variants (per community; CAP >= 2 * bound on distinct keys).
 constexpr int NB_AGG = 4;
@@ -56,12 +57,25 @@ struct MoveArgs {
     Ctl* ctl;
     int32_t* movers;      // SYNC: (vertex, target) pairs
     int32_t bucket;       // bucket id for per-bucket counters
-    // hub path
-    const int32_t* hubpos;   // static hub position of each hub vertex
-    const int64_t* hub_pre;  // prefix of hub table capacities over static positions
-    int32_t chunk_lo, chunk_hi;  // static positions whose tables are in the pool for this launch
+    const uint8_t* vbucket;
+    // hub path (static hub list of the pass, ascending vertex id)
+    const int32_t* hub_list;
+    const int64_t* hub_pre;  // prefix of table capacities over the static list
+    const int64_t* hch_pre;  // prefix of insert-chunk counts over the static list
+    int32_t g_lo, g_hi;      // hubs of this launch group (their tables fit the pool together)
+    int32_t all_queued;      // 1: every hub is queued (first iteration or no pruning)
+    uint32_t stamp_cur;      // stamp of the current iteration's queue
+    int32_t* gdec;           // per static hub: applied (ASYNC) or recorded (SYNC) target, or -1
     int32_t* hub_keys;
     void* hub_vals;
+};
+
+// Lists of buckets 0..3 for one fused launch; blk_pre[b] is the first block
+// of bucket b (blocks of 256 threads hold 256 / MOVE_G[b] vertices).
+struct FusedLists {
+    const int32_t* list[4];
+    int32_t count[4];
+    int64_t blk_pre[5];
 };
 
 struct Buckets {
@@ -89,13 +103,15 @@ void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint32_t* mark,
                         hipStream_t s);
 void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t count, i64* K, i64* Sig, Ctl* ctl,
                    hipStream_t s);
-void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, int32_t* hubpos,
+void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, int64_t* nch,
                      hipStream_t s);
 // mode: 0 = SYNC, 1 = ASYNC with cached loads, 2 = ASYNC with device-coherent loads/stores
 void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
                  hipStream_t s);
-void launch_move_hub(const LevelView& L, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
-                     hipStream_t s);
+void launch_hub_insert(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s);
+void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s);
+void launch_hub_mark(const LevelView& L, const MoveArgs& a, int64_t nchunks, hipStream_t s);
+void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const FusedLists& f, hipStream_t s);
 void launch_sync_apply(const LevelView& L, const MoveArgs& a, hipStream_t s);
 
 // ---- launchers: aggregation and modularity (lv_aggr.hip)

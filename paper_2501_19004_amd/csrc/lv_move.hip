@@ -181,8 +181,11 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_rowsum(Graph<OffT, WK> g,
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
     i64 s = 0;
-    if (active)
+    if constexpr (WK == 0) {
+        if (active && lane == 0) s = (i64)g.off[i + 1] - (i64)g.off[i];
+    } else if (active) {
         for (i64 e = (i64)g.off[i] + lane; e < (i64)g.off[i + 1]; e += G) s += g.weight(e);
+    }
     s = reduce_sum<G>(s, s_t);
     if (active && lane == 0) {
         K[i] = s;
@@ -197,7 +200,7 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_rowsum(Graph<OffT, WK> g,
 // 2 * (bound on distinct neighbour communities) = 2 * min(degree, n).
 template <typename OffT>
 __global__ void k_hub_caps(const OffT* __restrict__ off, int64_t n, const int32_t* __restrict__ list, int32_t count,
-                           int64_t* __restrict__ caps, int32_t* __restrict__ hubpos) {
+                           int64_t* __restrict__ caps, int64_t* __restrict__ nch) {
     const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= count) return;
     const int32_t v = list[h];
@@ -206,7 +209,7 @@ __global__ void k_hub_caps(const OffT* __restrict__ off, int64_t n, const int32_
     uint64_t cap = 1;
     while (cap < want) cap <<= 1;
     caps[h] = (int64_t)cap;
-    hubpos[v] = (int32_t)h;
+    nch[h] = (deg + HUB_CH - 1) / HUB_CH;
 }
 
 // ------------------------------------------------------------ local moving
@@ -319,27 +322,31 @@ __device__ __forceinline__ void add_block_totals(Ctl* ctl, int bucket, u64 ne, u
     }
 }
 
+// Block-level scratch shared by every local-moving path (sized for the
+// largest block, 1024 threads, and the most groups per block, 32).
+struct MoveShm {
+    i128 k128[16];
+    i64 k64[16];
+    int32_t d[16];
+    i64 v[16];
+    i64 t[16];
+    int32_t x[1];
+    i128 gain[32];
+    int32_t dec[32];
+    i64 arcs[32], nd[32];
+};
+
+// One block of a degree bucket: NG = BLOCK/G vertices, each evaluated by G
+// lanes with a CAP-slot table in LDS (keys/vals point at this block's LDS).
 template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE>
-__global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, const int32_t* __restrict__ list,
-                                                                int32_t count) {
+__device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __restrict__ list, int32_t count,
+                                           int64_t blk, int bucket, int32_t* s_keys, AccT* s_vals, MoveShm& sh) {
     constexpr int BLOCK = G > 256 ? G : 256;
     constexpr int NG = BLOCK / G;
     constexpr int L2C = Log2<CAP>::v;
-    __shared__ int32_t s_keys[NG * CAP];
-    __shared__ AccT s_vals[NG * CAP];
-    __shared__ i128 s_k128[BLOCK / WAVE];
-    __shared__ i64 s_k64[BLOCK / WAVE];
-    __shared__ int32_t s_d[BLOCK / WAVE];
-    __shared__ i64 s_v[BLOCK / WAVE];
-    __shared__ i64 s_t[BLOCK / WAVE];
-    __shared__ int32_t s_x[1];
-    __shared__ i128 s_gain[NG];
-    __shared__ int32_t s_dec[NG];
-    __shared__ i64 s_arcs[NG], s_nd[NG];
-
     const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-    const int64_t slot = (int64_t)blockIdx.x * NG + grp;
+    const int64_t slot = blk * NG + grp;
     const bool active = slot < count;
     const int32_t i = active ? list[slot] : -1;
     int32_t* keys = s_keys + grp * CAP;
@@ -364,87 +371,202 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
     group_sync<G>();
 
     Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, keys, vals, CAP, lane, active, c, Ki, s_k64, s_d, s_v, s_t)
-        : decide<G, MODE, i128, AccT>(a, keys, vals, CAP, lane, active, c, Ki, s_k128, s_d, s_v, s_t);
+        ? decide<G, MODE, i64, AccT>(a, keys, vals, CAP, lane, active, c, Ki, sh.k64, sh.d, sh.v, sh.t)
+        : decide<G, MODE, i128, AccT>(a, keys, vals, CAP, lane, active, c, Ki, sh.k128, sh.d, sh.v, sh.t);
 
     if constexpr (MODE == M_SYNC) {
         wave_append_pair(lane == 0 && dcs.target >= 0, i, dcs.target, a.movers, &a.ctl->movers);
     } else {
         int32_t t = -1;
         if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, i, c, Ki, dcs)) t = dcs.target;
-        t = group_bcast<G>(t, s_x);
+        t = group_bcast<G>(t, sh.x);
         if (a.prune && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
     }
     if (lane == 0) {
-        s_gain[grp] = dcs.gain;
-        s_dec[grp] = dcs.target;
-        s_arcs[grp] = active ? (o1 - o0) : -1;
-        s_nd[grp] = dcs.nd;
+        sh.gain[grp] = dcs.gain;
+        sh.dec[grp] = dcs.target;
+        sh.arcs[grp] = active ? (o1 - o0) : -1;
+        sh.nd[grp] = dcs.nd;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         i128 sg = 0;
         u64 nm = 0, ne = 0, na = 0, ndt = 0, nma = 0;
         for (int k = 0; k < NG; k++) {
-            if (s_arcs[k] < 0) continue;
+            if (sh.arcs[k] < 0) continue;
             ne++;
-            na += (u64)s_arcs[k];
-            ndt += (u64)s_nd[k];
-            if (s_dec[k] >= 0) { sg += s_gain[k]; nm++; nma += (u64)s_arcs[k]; }
+            na += (u64)sh.arcs[k];
+            ndt += (u64)sh.nd[k];
+            if (sh.dec[k] >= 0) { sg += sh.gain[k]; nm++; nma += (u64)sh.arcs[k]; }
         }
-        add_block_totals(a.ctl, a.bucket, ne, na, ndt, nm, nma, sg);
+        add_block_totals(a.ctl, bucket, ne, na, ndt, nm, nma, sg);
     }
 }
 
-// Hub path: one 1024-thread workgroup per queued hub, table in a global pool
-// at the hub's static position; hubs outside this launch's chunk exit.
+template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE>
+__global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, const int32_t* __restrict__ list,
+                                                                int32_t count) {
+    constexpr int NG = (G > 256 ? G : 256) / G;
+    __shared__ int32_t s_keys[NG * CAP];
+    __shared__ AccT s_vals[NG * CAP];
+    __shared__ MoveShm sh;
+    move_block<OffT, WK, AccT, G, CAP, MODE>(a, list, count, blockIdx.x, a.bucket, s_keys, s_vals, sh);
+}
+
+// Buckets 0..3 (all 256-thread blocks) in one launch: block ranges
+// [blk_pre[b], blk_pre[b+1]) belong to bucket b; the tables live in dynamic
+// LDS sized for the largest of the four.
 template <typename OffT, int WK, typename AccT, int MODE>
-__global__ void __launch_bounds__(HUB_G) k_move_hub(MoveArgs a, const int32_t* __restrict__ list, int32_t count) {
-    constexpr int G = HUB_G;
+__global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
+    extern __shared__ __align__(16) char dyn[];
+    __shared__ MoveShm sh;
+    const int64_t b = (int64_t)blockIdx.x;
+    int bk = 0;
+    while (bk < 3 && b >= f.blk_pre[bk + 1]) bk++;
+    const int64_t blk = b - f.blk_pre[bk];
+    switch (bk) {
+        case 0: {
+            constexpr int NG = 256 / MOVE_G[0];
+            move_block<OffT, WK, AccT, MOVE_G[0], MOVE_CAP[0], MODE>(
+                a, f.list[0], f.count[0], blk, 0, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[0] * 4), sh);
+            break;
+        }
+        case 1: {
+            constexpr int NG = 256 / MOVE_G[1];
+            move_block<OffT, WK, AccT, MOVE_G[1], MOVE_CAP[1], MODE>(
+                a, f.list[1], f.count[1], blk, 1, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[1] * 4), sh);
+            break;
+        }
+        case 2: {
+            constexpr int NG = 256 / MOVE_G[2];
+            move_block<OffT, WK, AccT, MOVE_G[2], MOVE_CAP[2], MODE>(
+                a, f.list[2], f.count[2], blk, 2, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[2] * 4), sh);
+            break;
+        }
+        default: {
+            constexpr int NG = 256 / MOVE_G[3];
+            move_block<OffT, WK, AccT, MOVE_G[3], MOVE_CAP[3], MODE>(
+                a, f.list[3], f.count[3], blk, 3, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[3] * 4), sh);
+            break;
+        }
+    }
+}
+
+// ------------------------------------------------------------ hubs
+// Vertices above the largest LDS bucket are processed once per iteration,
+// before the other buckets, by three launches: (1) chunks of HUB_CH arcs,
+// one workgroup each, accumulate K_{i->d} in an LDS table and add it into the
+// hub's global table; (2) one workgroup per hub scans its table, decides and
+// (ASYNC) applies the move, then clears the table; (3) chunks of the movers'
+// rows stamp their neighbours.  Queued hubs: all in the first iteration of a
+// pass (or without pruning), else those stamped by the previous iteration.
+__device__ __forceinline__ bool hub_queued(const MoveArgs& a, int32_t v) {
+    return a.all_queued || a.mark[v] == a.stamp_cur;
+}
+// largest h in [0, n) with pre[h] - base <= x
+__device__ __forceinline__ int32_t owner_of(const int64_t* pre, int32_t n, int64_t base, int64_t x) {
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] - base <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename OffT, int WK, typename AccT, int MODE>
+__global__ void __launch_bounds__(1024) k_hub_insert(MoveArgs a) {
+    constexpr int G = 1024;
+    constexpr int L2C = Log2<HUB_LCAP>::v;
+    __shared__ int32_t s_keys[HUB_LCAP];
+    __shared__ AccT s_vals[HUB_LCAP];
+    const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
+    const int32_t ng = a.g_hi - a.g_lo;
+    const int64_t chunk_base = a.hch_pre[a.g_lo];
+    const int32_t h = a.g_lo + owner_of(a.hch_pre + a.g_lo, ng, chunk_base, blockIdx.x);
+    const int32_t v = a.hub_list[h];
+    if (!hub_queued(a, v)) return;  // uniform per block
+    const int tid = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x - (a.hch_pre[h] - chunk_base);
+    const i64 e0 = (i64)g.off[v] + k * HUB_CH;
+    const i64 e1 = min(e0 + (i64)HUB_CH, (i64)g.off[v + 1]);
+    for (int s = tid; s < HUB_LCAP; s += G) { s_keys[s] = EMPTY_KEY; s_vals[s] = 0; }
+    __syncthreads();
+    for (i64 e = e0 + tid; e < e1; e += G) {
+        const int32_t j = g.idx[e];
+        if (j == v) continue;
+        const int32_t d = ld_c<MODE>(&a.Cp[j]);
+        table_add<AccT>(s_keys, s_vals, HUB_LCAP - 1, hash_slot<L2C>(d), d, (AccT)g.weight(e));
+    }
+    __syncthreads();
+    const int64_t toff = a.hub_pre[h] - a.hub_pre[a.g_lo];
+    const int64_t cap = a.hub_pre[h + 1] - a.hub_pre[h];
+    const int log2cap = __ffsll((long long)cap) - 1;
+    int32_t* keys = a.hub_keys + toff;
+    AccT* vals = (AccT*)a.hub_vals + toff;
+    for (int s = tid; s < HUB_LCAP; s += G) {
+        const int32_t d = s_keys[s];
+        if (d != EMPTY_KEY) table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d, s_vals[s]);
+    }
+}
+
+template <typename OffT, int WK, typename AccT, int MODE>
+__global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
+    constexpr int G = 1024;
     __shared__ i128 s_k128[G / WAVE];
     __shared__ i64 s_k64[G / WAVE];
     __shared__ int32_t s_d[G / WAVE];
     __shared__ i64 s_v[G / WAVE];
     __shared__ i64 s_t[G / WAVE];
-    __shared__ int32_t s_x[1];
-    const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
-    const int64_t slot = blockIdx.x;
-    if (slot >= count) return;
-    const int32_t i = list[slot];
-    const int32_t pos = a.hubpos[i];
-    if (pos < a.chunk_lo || pos >= a.chunk_hi) return;  // uniform per block
-    const int lane = threadIdx.x;
-    const int64_t toff = a.hub_pre[pos] - a.hub_pre[a.chunk_lo];
-    const int64_t cap = a.hub_pre[pos + 1] - a.hub_pre[pos];
-    const int log2cap = __ffsll((long long)cap) - 1;
+    const OffT* off = (const OffT*)a.off;
+    const int32_t h = a.g_lo + blockIdx.x;
+    const int32_t v = a.hub_list[h];
+    const int tid = threadIdx.x;
+    if (!hub_queued(a, v)) {
+        if (tid == 0) a.gdec[h] = -1;
+        return;
+    }
+    const int64_t toff = a.hub_pre[h] - a.hub_pre[a.g_lo];
+    const int64_t cap = a.hub_pre[h + 1] - a.hub_pre[h];
     int32_t* keys = a.hub_keys + toff;
     AccT* vals = (AccT*)a.hub_vals + toff;
-    for (int64_t s = lane; s < cap; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }
-    __syncthreads();
-    const int32_t c = ld_c<MODE>(&a.Cp[i]);
-    const i64 Ki = a.K[i];
-    const i64 o0 = (i64)g.off[i], o1 = (i64)g.off[i + 1];
-    for (i64 e = o0 + lane; e < o1; e += G) {
-        const int32_t j = g.idx[e];
-        if (j == i) continue;
-        const int32_t d = ld_c<MODE>(&a.Cp[j]);
-        table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d, (AccT)g.weight(e));
-    }
-    __syncthreads();
+    const int32_t c = ld_c<MODE>(&a.Cp[v]);
+    const i64 Ki = a.K[v];
     Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, keys, vals, cap, lane, true, c, Ki, s_k64, s_d, s_v, s_t)
-        : decide<G, MODE, i128, AccT>(a, keys, vals, cap, lane, true, c, Ki, s_k128, s_d, s_v, s_t);
-    if constexpr (MODE == M_SYNC) {
-        wave_append_pair(lane == 0 && dcs.target >= 0, i, dcs.target, a.movers, &a.ctl->movers);
-    } else {
-        int32_t t = -1;
-        if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, i, c, Ki, dcs)) t = dcs.target;
-        t = group_bcast<G>(t, s_x);
-        if (a.prune && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
+        ? decide<G, MODE, i64, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k64, s_d, s_v, s_t)
+        : decide<G, MODE, i128, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k128, s_d, s_v, s_t);
+    for (int64_t s = tid; s < cap; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }  // clean for the next iteration
+    const i64 deg = (i64)off[v + 1] - (i64)off[v];
+    if (tid == 0) {
+        if constexpr (MODE == M_SYNC) {
+            if (dcs.target >= 0) {
+                const int32_t r = atomicAdd(&a.ctl->movers, 1);
+                a.movers[2 * (int64_t)r] = v;
+                a.movers[2 * (int64_t)r + 1] = dcs.target;
+            }
+        } else {
+            if (dcs.target >= 0) apply_async<MODE>(a, v, c, Ki, dcs);
+        }
+        a.gdec[h] = dcs.target;
+        add_block_totals(a.ctl, a.bucket, 1, (u64)deg, (u64)dcs.nd, dcs.target >= 0 ? 1 : 0,
+                         dcs.target >= 0 ? (u64)deg : 0, dcs.gain);
     }
-    if (lane == 0)
-        add_block_totals(a.ctl, a.bucket, 1, (u64)(o1 - o0), (u64)dcs.nd, dcs.target >= 0 ? 1 : 0,
-                         dcs.target >= 0 ? (u64)(o1 - o0) : 0, dcs.gain);
+}
+
+template <typename OffT>
+__global__ void __launch_bounds__(1024) k_hub_mark(MoveArgs a) {
+    const int32_t ng = a.g_hi - a.g_lo;
+    const int64_t chunk_base = a.hch_pre[a.g_lo];
+    const int32_t h = a.g_lo + owner_of(a.hch_pre + a.g_lo, ng, chunk_base, blockIdx.x);
+    if (a.gdec[h] < 0) return;
+    const OffT* off = (const OffT*)a.off;
+    const int32_t v = a.hub_list[h];
+    const int64_t k = (int64_t)blockIdx.x - (a.hch_pre[h] - chunk_base);
+    const i64 e0 = (i64)off[v] + k * HUB_CH;
+    const i64 e1 = min(e0 + (i64)HUB_CH, (i64)off[v + 1]);
+    for (i64 e = e0 + threadIdx.x; e < e1; e += 1024) {
+        const int32_t j = a.idx[e];
+        if (j != v && a.mark[j] != a.stamp_next) a.mark[j] = a.stamp_next;
+    }
 }
 
 // SYNC: apply the recorded decisions together, then stamp the movers'
@@ -464,7 +586,7 @@ __global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a) {
             atomicAdd((u64*)&a.Sig[d], (u64)Ki);
             a.Cp[i] = d;
         }
-        if (a.prune) mark_neighbours<WAVE>(a, g, i, (i64)g.off[i], (i64)g.off[i + 1], lane);
+        if (a.prune && a.vbucket[i] != NB_MOVE) mark_neighbours<WAVE>(a, g, i, (i64)g.off[i], (i64)g.off[i + 1], lane);
     }
 }
 
@@ -526,15 +648,13 @@ void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t 
     });
 }
 
-void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, int32_t* hubpos,
+void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, int64_t* nch,
                      hipStream_t s) {
     if (count <= 0) return;
     if (L.t.off64)
-        k_hub_caps<int64_t><<<blocks_for(count, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, list, count, caps,
-                                                                    hubpos);
+        k_hub_caps<int64_t><<<blocks_for(count, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, list, count, caps, nch);
     else
-        k_hub_caps<int32_t><<<blocks_for(count, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, list, count, caps,
-                                                                    hubpos);
+        k_hub_caps<int32_t><<<blocks_for(count, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, list, count, caps, nch);
 }
 
 void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
@@ -564,17 +684,50 @@ void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, co
     });
 }
 
-void launch_move_hub(const LevelView& L, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
-                     hipStream_t s) {
-    if (count <= 0) return;
+void launch_hub_insert(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s) {
+    if (nchunks <= 0) return;
     dispatch_types(L.t, [&](auto o, auto w, auto ac) {
         using OffT = typename decltype(o)::type;
         constexpr int WK = decltype(w)::value;
         using AccT = typename decltype(ac)::type;
-        if (mode == M_SYNC) k_move_hub<OffT, WK, AccT, M_SYNC><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
-        else if (mode == M_ASYNC_CACHED)
-            k_move_hub<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
-        else k_move_hub<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)count, HUB_G, 0, s>>>(a, list, count);
+        if (mode == M_SYNC) k_hub_insert<OffT, WK, AccT, M_SYNC><<<(unsigned)nchunks, 1024, 0, s>>>(a);
+        else if (mode == M_ASYNC_CACHED) k_hub_insert<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)nchunks, 1024, 0, s>>>(a);
+        else k_hub_insert<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)nchunks, 1024, 0, s>>>(a);
+    });
+}
+
+void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s) {
+    const int32_t nh = a.g_hi - a.g_lo;
+    if (nh <= 0) return;
+    dispatch_types(L.t, [&](auto o, auto w, auto ac) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        using AccT = typename decltype(ac)::type;
+        if (mode == M_SYNC) k_hub_decide<OffT, WK, AccT, M_SYNC><<<(unsigned)nh, 1024, 0, s>>>(a);
+        else if (mode == M_ASYNC_CACHED) k_hub_decide<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)nh, 1024, 0, s>>>(a);
+        else k_hub_decide<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)nh, 1024, 0, s>>>(a);
+    });
+}
+
+void launch_hub_mark(const LevelView& L, const MoveArgs& a, int64_t nchunks, hipStream_t s) {
+    if (nchunks <= 0) return;
+    if (L.t.off64) k_hub_mark<int64_t><<<(unsigned)nchunks, 1024, 0, s>>>(a);
+    else k_hub_mark<int32_t><<<(unsigned)nchunks, 1024, 0, s>>>(a);
+}
+
+void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const FusedLists& f, hipStream_t s) {
+    const int64_t grid = f.blk_pre[4];
+    if (grid <= 0) return;
+    dispatch_types(L.t, [&](auto o, auto w, auto ac) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        using AccT = typename decltype(ac)::type;
+        size_t shm = 0;
+        for (int b = 0; b < 4; b++)
+            shm = std::max(shm, (size_t)(256 / MOVE_G[b]) * MOVE_CAP[b] * (4 + sizeof(AccT)));
+        if (mode == M_SYNC) k_move_fused<OffT, WK, AccT, M_SYNC><<<(unsigned)grid, 256, shm, s>>>(a, f);
+        else if (mode == M_ASYNC_CACHED) k_move_fused<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)grid, 256, shm, s>>>(a, f);
+        else k_move_fused<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)grid, 256, shm, s>>>(a, f);
     });
 }
 
