@@ -25,9 +25,6 @@ _SRC = os.path.join(_HERE, "louvain_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-ASYNC = 0
-SYNC = 1
-
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C11, no vectorisation tricks)."""
@@ -42,12 +39,14 @@ class _Params(ctypes.Structure):
     _fields_ = [("max_iterations", ctypes.c_int32), ("max_passes", ctypes.c_int32),
                 ("tol_num", ctypes.c_int64), ("tol_den", ctypes.c_int64), ("tol_drop", ctypes.c_int64),
                 ("agg_num", ctypes.c_int64), ("agg_den", ctypes.c_int64),
-                ("mode", ctypes.c_int32), ("pick_less", ctypes.c_int32), ("prune", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("pick_less", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("guard_tolerance", ctypes.c_int32), ("mlp", ctypes.POINTER(ctypes.c_float)),
+                ("threshold", ctypes.c_double), ("sample_per_mille", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("iterations", ctypes.c_int32), ("moves", ctypes.c_int64),
-                ("communities", ctypes.c_int64)]
+                ("communities", ctypes.c_int64), ("sweeps", ctypes.c_int64), ("pruned", ctypes.c_int64)]
 
 
 _I64P = ctypes.POINTER(ctypes.c_int64)
@@ -57,6 +56,13 @@ _ITER_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int3
                             ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64)
 _PASS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, _I64P, _I32P, _I64P,
                             ctypes.c_int32)
+_F32P = ctypes.POINTER(ctypes.c_float)
+_SAMPLE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _F32P,
+                              ctypes.c_int32)
+
+ASYNC, SYNC = 0, 1
+PRUNE_NONE, PRUNE_FLAGS, PRUNE_LEARNED = 0, 1, 2
+MLP_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1
 
 
 def _load():
@@ -70,6 +76,15 @@ def _load():
         lib.oracle_louvain.restype = ctypes.c_int
         lib.oracle_louvain.argtypes = [ctypes.c_int64, _I64P, _I32P, _I64P, ctypes.POINTER(_Params), _I32P,
                                        ctypes.POINTER(_Stats), _ITER_FN, _PASS_FN, ctypes.c_void_p]
+        lib.oracle_louvain_samples.restype = ctypes.c_int
+        lib.oracle_louvain_samples.argtypes = [ctypes.c_int64, _I64P, _I32P, _I64P, ctypes.POINTER(_Params), _I32P,
+                                               ctypes.POINTER(_Stats), _ITER_FN, _PASS_FN, _SAMPLE_FN,
+                                               ctypes.c_void_p]
+        lib.oracle_mlp_logit.restype = ctypes.c_float
+        lib.oracle_mlp_logit.argtypes = [_F32P, _F32P]
+        lib.oracle_features.restype = None
+        lib.oracle_features.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F32P]
         lib.oracle_aggregate.restype = ctypes.c_int
         lib.oracle_aggregate.argtypes = [ctypes.c_int64, _I64P, _I32P, _I64P, _I32P, ctypes.c_int64, _I64P, _I32P,
                                          _I64P]
@@ -114,10 +129,22 @@ class Params:
     mode: int = ASYNC
     pick_less: int = 4
     prune: int = 1
+    guard_tolerance: int = 1          # PRUNE_LEARNED: sweep exit test (0 strict, 1 tolerance)
+    mlp: np.ndarray | None = None     # PRUNE_LEARNED: MLP_PARAMS float32 weights
+    threshold: float = 0.5            # PRUNE_LEARNED: evaluate iff sigmoid(logit) >= threshold
+    sample_per_mille: int = 0         # training-sample selection rate
 
     def _c(self) -> _Params:
+        mlp = None
+        if self.mlp is not None:
+            mlp = np.ascontiguousarray(self.mlp, dtype=np.float32)
+            if mlp.size != MLP_PARAMS:
+                raise ValueError(f"mlp must hold {MLP_PARAMS} floats")
+        self._mlp_keep = mlp
         return _Params(self.max_iterations, self.max_passes, self.tol_num, self.tol_den, self.tol_drop,
-                       self.agg_num, self.agg_den, self.mode, self.pick_less, self.prune)
+                       self.agg_num, self.agg_den, self.mode, self.pick_less, self.prune, self.guard_tolerance,
+                       _p(mlp, ctypes.c_float) if mlp is not None else None, float(self.threshold),
+                       self.sample_per_mille)
 
 
 @dataclasses.dataclass
@@ -129,6 +156,9 @@ class Result:
     communities: int
     iters: list = dataclasses.field(default_factory=list)   # per-iteration trace records
     graphs: list = dataclasses.field(default_factory=list)  # per-pass super-graphs
+    sweeps: int = 0
+    pruned: int = 0
+    samples: list = dataclasses.field(default_factory=list)  # (pass, iter, v, features float32[8], label)
 
 
 def modularity_exact(g, membership) -> Fraction:
@@ -162,9 +192,11 @@ def modularity(g, membership) -> float:
     return float(q)
 
 
-def louvain(g, params: Params | None = None, trace: bool = False) -> Result:
+def louvain(g, params: Params | None = None, trace: bool = False, samples: bool = False) -> Result:
     """Run the oracle.  With trace=True, records (pass, iter, C', Sigma', moves,
-    gain sum) after every local-moving iteration and every super-graph."""
+    gain sum) after every local-moving iteration and every super-graph.  With
+    samples=True, records the training samples selected by
+    params.sample_per_mille."""
     params = params or Params()
     off, idx, w = _arrays(g)
     memb = np.empty(g.n, dtype=np.int32)
@@ -184,14 +216,42 @@ def louvain(g, params: Params | None = None, trace: bool = False) -> Result:
         www = np.ctypeslib.as_array(ww, shape=(max(nnz, 1),))[:nnz].copy() if nnz else np.zeros(0, np.int64)
         graphs.append(dict(pass_=p, n=int(n), offsets=oo, indices=ii, weights=www, iterations=int(count)))
 
+    smp: list = []
+
+    def on_sample(_u, p, t, v, f, label):
+        smp.append((int(p), int(t), int(v), np.ctypeslib.as_array(f, shape=(8,)).copy(), int(label)))
+
     it_fn = _ITER_FN(on_iter) if trace else _ITER_FN()
     pa_fn = _PASS_FN(on_pass) if trace else _PASS_FN()
+    sm_fn = _SAMPLE_FN(on_sample) if samples else _SAMPLE_FN()
     cp = params._c()
-    rc = _load().oracle_louvain(g.n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32), _p(w, ctypes.c_int64),
-                                ctypes.byref(cp), _p(memb, ctypes.c_int32), ctypes.byref(st), it_fn, pa_fn, None)
+    rc = _load().oracle_louvain_samples(g.n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32),
+                                        _p(w, ctypes.c_int64), ctypes.byref(cp), _p(memb, ctypes.c_int32),
+                                        ctypes.byref(st), it_fn, pa_fn, sm_fn, None)
     if rc != 0:
         raise RuntimeError(f"oracle_louvain failed ({rc})")
-    return Result(memb, st.passes, st.iterations, st.moves, st.communities, iters, graphs)
+    return Result(memb, st.passes, st.iterations, st.moves, st.communities, iters, graphs, st.sweeps, st.pruned,
+                  smp)
+
+
+def mlp_logit(weights, x) -> np.ndarray:
+    """FP32 output logits of the pruner MLP for rows of x (float32 [k, 8]),
+    with the oracle's fixed fused-multiply-add order."""
+    wts = np.ascontiguousarray(weights, dtype=np.float32)
+    xs = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+    lib = _load()
+    out = np.empty(xs.shape[0], dtype=np.float32)
+    for k in range(xs.shape[0]):
+        row = np.ascontiguousarray(xs[k])
+        out[k] = lib.oracle_mlp_logit(_p(wts, ctypes.c_float), _p(row, ctypes.c_float))
+    return out
+
+
+def features(deg: int, K: int, own: int, adv: int, nm: int, moved_last: bool, pass_: int, t: int) -> np.ndarray:
+    """The eight float32 pruner features of one vertex from its state."""
+    f = np.zeros(8, dtype=np.float32)
+    _load().oracle_features(deg, K, own, adv, nm, 1 if moved_last else 0, pass_, t, _p(f, ctypes.c_float))
+    return f
 
 
 def aggregate(g, cprime, ncom: int):

@@ -17,7 +17,11 @@
  *     snapshot variant of Algorithm 5 (SYNC mode: every flagged vertex decides
  *     against the start-of-iteration state, Pick-Less every rho iterations,
  *     then all moves are applied together);
- *   - the aggregation phase of Algorithm 3 / Algorithm 6.
+ *   - the aggregation phase of Algorithm 3 / Algorithm 6;
+ *   - a learned move-pruner generalising the paper's vertex pruning (its
+ *     Optimizations section): an MLP over eight per-vertex features decides
+ *     which flagged vertices are evaluated, and a pass may only end after an
+ *     unpruned sweep over every vertex passes the exit test.
  *
  * Notation (paper, Preliminaries): W = sum over stored arcs of w = 2m.
  * K_i = weighted degree (a self-loop arc counts once), K_{i->d} = weight from
@@ -29,6 +33,7 @@
  * __int128.  Parity unpinned: none -- every function is pinned by the CPU
  * tests (brute force, closed forms, invariants, library routines).
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -50,7 +55,13 @@ typedef struct {
     int64_t agg_num, agg_den; /* aggregation tolerance tau_agg = agg_num/agg_den (paper: 0.8) */
     int32_t mode;             /* 0 = ASYNC, 1 = SYNC */
     int32_t pick_less;        /* rho for SYNC mode, 0 = off (paper: 4) */
-    int32_t prune;            /* 1 = vertex pruning (paper default), 0 = every vertex every iteration */
+    int32_t prune;            /* 1 = vertex pruning (paper default), 0 = every vertex every iteration,
+                                 2 = vertex pruning filtered by the learned MLP, with sweep guard */
+    int32_t guard_tolerance;  /* prune 2: a sweep ends the pass if no evaluated vertex has a positive best
+                                 gain (0), or if the sweep's gain sum passes the tolerance test (1) */
+    const float* mlp;         /* prune 2: OG_MLP_PARAMS weights (layout at mlp_logit) */
+    double threshold;         /* prune 2: a flagged vertex is evaluated iff sigmoid(logit) >= threshold */
+    int32_t sample_per_mille; /* sample selection rate for the sample callback (0 = none) */
 } og_params;
 
 typedef struct {
@@ -58,11 +69,16 @@ typedef struct {
     int32_t iterations;       /* local-moving iterations over all passes */
     int64_t moves;            /* vertex moves applied over all passes */
     int64_t communities;      /* final number of communities */
+    int64_t sweeps;           /* prune 2: iterations that evaluated every vertex (first ones included) */
+    int64_t pruned;           /* prune 2: flagged vertices the MLP skipped */
 } og_stats;
 
 /* Per-iteration trace: state after the iteration's moves are applied. */
 typedef void (*og_iter_fn)(void* user, int32_t pass, int32_t iter, int64_t n, const int32_t* cprime,
                            const int64_t* sigma, int64_t moves, int64_t gain_hi, uint64_t gain_lo);
+/* Training sample: features of an evaluated vertex before the iteration and
+ * whether it then moved. */
+typedef void (*og_sample_fn)(void* user, int32_t pass, int32_t iter, int64_t v, const float* feat, int32_t label);
 /* Per-pass trace: the super-vertex graph produced by aggregation. */
 typedef void (*og_pass_fn)(void* user, int32_t pass, int64_t n, const int64_t* off, const int32_t* idx,
                            const int64_t* w, int32_t count);
@@ -158,23 +174,117 @@ static i128 move_gain(int64_t W, int64_t Ki, int64_t Kid, int64_t Kic, int64_t S
  * fills (best_d, best_gain) when a candidate exists, 0 otherwise.
  */
 static int best_move(const og_graph* g, int64_t W, const int32_t* C, const int64_t* Sig, const int64_t* K,
-                     int64_t i, scratch* s, int32_t* best_d, i128* best_gain) {
+                     int64_t i, scratch* s, int32_t* best_d, i128* best_gain, int64_t* kic, int64_t* kid) {
     int64_t nt = scan_communities(g, C, i, s);
     int32_t c = C[i];
     int64_t Kic = s->acc[c];
     int found = 0;
     i128 bg = 0;
     int32_t bd = -1;
+    int64_t bk = 0;
     for (int64_t k = 0; k < nt; k++) {
         int32_t d = s->touched[k];
         if (d == c) continue;
         i128 gain = move_gain(W, K[i], s->acc[d], Kic, Sig[d], Sig[c]);
-        if (!found || gain > bg || (gain == bg && d < bd)) { bg = gain; bd = d; found = 1; }
+        if (!found || gain > bg || (gain == bg && d < bd)) { bg = gain; bd = d; bk = s->acc[d]; found = 1; }
     }
     clear_scan(s, nt);
     *best_d = bd;
     *best_gain = bg;
+    *kic = Kic;
+    *kid = bk;
     return found;
+}
+
+/* ------------------------------------------------ learned move pruner */
+
+#define OG_MLP_IN 8
+#define OG_MLP_H 32
+#define OG_MLP_PARAMS (OG_MLP_H * OG_MLP_IN + OG_MLP_H + OG_MLP_H * OG_MLP_H + OG_MLP_H + OG_MLP_H + 1)
+
+/* Per-vertex state of the current pass from which the features are formed. */
+typedef struct {
+    int64_t* own;      /* K_{v->C'[v]} at v's last evaluation */
+    int64_t* adv;      /* K_{v->d*} - K_{v->C'[v]} at v's last evaluation, d* = best candidate (K = 0 if none) */
+    int32_t* moved_at; /* last iteration of the pass in which v moved, -1 if none */
+    int32_t* nm_prev;  /* neighbours of v that moved in the previous iteration */
+    int32_t* nm_cur;   /* neighbours of v that moved so far in this iteration */
+} learn_state;
+
+/* Piecewise-linear base-2 logarithm of an integer x >= 1 (Mitchell, 1962):
+ * with e = floor(log2 x), e + (x - 2^e) / 2^e; exact at powers of two. */
+static float mitchell_log2(int64_t x) {
+    int e = 0;
+    while ((x >> (e + 1)) != 0) e++;
+    int64_t p = (int64_t)1 << e;
+    float frac = (float)(x - p) / (float)p;
+    return (float)e + frac;
+}
+
+/* The eight FP32 features of vertex v at the start of iteration t of pass p. */
+static void features(const og_graph* g, const int64_t* K, const learn_state* L, int64_t v, int32_t pass,
+                     int32_t t, float* f) {
+    int64_t deg = g->off[v + 1] - g->off[v];
+    int32_t m = L->nm_prev[v];
+    f[0] = mitchell_log2(1 + deg) / 16.0f;
+    f[1] = K[v] > 0 ? (float)L->own[v] / (float)K[v] : 0.0f;
+    f[2] = mitchell_log2(1 + (int64_t)m) / 16.0f;
+    f[3] = deg > 0 ? (float)m / (float)deg : 0.0f;
+    f[4] = L->moved_at[v] == t - 1 ? 1.0f : 0.0f;
+    f[5] = (float)pass / 10.0f;
+    f[6] = (float)t / 20.0f;
+    f[7] = K[v] > 0 ? (float)L->adv[v] / (float)K[v] : 0.0f;
+}
+
+/* MLP 8 -> 32 -> 32 -> 1 with ReLU hidden layers; returns the output logit.
+ * Weights: W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3.  Every
+ * neuron starts from its bias and adds its inputs in index order with fused
+ * multiply-adds, so the FP32 result is fully specified. */
+float oracle_mlp_logit(const float* P, const float* x) {
+    const float* W1 = P;
+    const float* b1 = W1 + OG_MLP_H * OG_MLP_IN;
+    const float* W2 = b1 + OG_MLP_H;
+    const float* b2 = W2 + OG_MLP_H * OG_MLP_H;
+    const float* w3 = b2 + OG_MLP_H;
+    const float b3 = w3[OG_MLP_H];
+    float h1[OG_MLP_H], h2[OG_MLP_H];
+    for (int k = 0; k < OG_MLP_H; k++) {
+        float a = b1[k];
+        for (int j = 0; j < OG_MLP_IN; j++) a = fmaf(W1[k * OG_MLP_IN + j], x[j], a);
+        h1[k] = a > 0.0f ? a : 0.0f;
+    }
+    for (int k = 0; k < OG_MLP_H; k++) {
+        float a = b2[k];
+        for (int j = 0; j < OG_MLP_H; j++) a = fmaf(W2[k * OG_MLP_H + j], h1[j], a);
+        h2[k] = a > 0.0f ? a : 0.0f;
+    }
+    float z = b3;
+    for (int j = 0; j < OG_MLP_H; j++) z = fmaf(w3[j], h2[j], z);
+    return z;
+}
+
+/* sigmoid(z) >= theta  <=>  z >= log(theta / (1 - theta)); theta <= 0 keeps
+ * every vertex, theta >= 1 none (short of an infinite logit). */
+static float logit_threshold(double theta) {
+    if (theta <= 0.0) return -INFINITY;
+    if (theta >= 1.0) return INFINITY;
+    return (float)log(theta / (1.0 - theta));
+}
+
+/* SplitMix64 output function (Steele, Lea, Flood 2014) of one counter value. */
+static uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Training-sample selection: vertex v at (pass, iteration) is recorded iff
+ * splitmix64(key) mod 1000 < per_mille, key = v + 2^32 * (pass * 2^16 + t). */
+static int sample_selected(int64_t v, int32_t pass, int32_t t, int32_t per_mille) {
+    if (per_mille <= 0) return 0;
+    uint64_t key = (uint64_t)v + ((uint64_t)((uint32_t)pass * 65536u + (uint32_t)t) << 32);
+    return (int32_t)(splitmix64(key) % 1000u) < per_mille;
 }
 
 /* Tolerance test of the local-moving loop: converged iff
@@ -191,33 +301,104 @@ static int converged(i128 S, int64_t W, const og_params* P, int32_t pass) {
     return lhs <= rhs;
 }
 
-/* Local-moving phase.  Returns the number of iterations performed. */
+/* Record vertex i's outcome in the learned-pruner state: its last
+ * evaluation (own-community weight and best-candidate advantage). */
+static void note_evaluation(learn_state* L, int64_t i, int found, int64_t kic, int64_t kid) {
+    L->own[i] = kic;
+    L->adv[i] = (found ? kid : 0) - kic;
+}
+
+/* Record a move of i in iteration t: i moved, and each neighbour j != i has
+ * one more moved neighbour in this iteration. */
+static void note_move(const og_graph* g, learn_state* L, int64_t i, int32_t t) {
+    L->moved_at[i] = t;
+    for (int64_t e = g->off[i]; e < g->off[i + 1]; e++)
+        if (g->idx[e] != i) L->nm_cur[g->idx[e]]++;
+}
+
+/*
+ * Local-moving phase.  Returns the number of iterations performed.
+ *
+ * prune = 0: every vertex is evaluated in every iteration.  prune = 1: the
+ * paper's vertex pruning -- all vertices start flagged, an evaluated vertex
+ * is unflagged, a mover flags its neighbours.  prune = 2: as 1, but in
+ * iterations that are not sweeps a flagged vertex is evaluated only if the
+ * MLP, given its features at that point, reaches the threshold (else it is
+ * unflagged without evaluation); a sweep evaluates every vertex.  Iteration
+ * 0 is a sweep; so is an iteration whose pruned queue would be empty, and
+ * the iteration after a non-sweep iteration that passes the tolerance test.
+ * The pass ends only at a sweep that passes the exit test (guard_tolerance
+ * 0: no evaluated vertex had a positive best gain; 1: the tolerance test),
+ * or after max_iterations.
+ */
 static int32_t local_move(const og_graph* g, int64_t W, int32_t* C, int64_t* Sig, const int64_t* K,
                           const og_params* P, int32_t pass, scratch* s, uint8_t* flag, int32_t* dec,
-                          i128* gains, og_stats* st, og_iter_fn it_cb, void* user) {
+                          i128* gains, learn_state* L, og_stats* st, og_iter_fn it_cb, og_sample_fn sm_cb,
+                          void* user) {
     int64_t n = g->n;
+    const int learned = P->prune == 2;
+    const int track = learned || (sm_cb && P->sample_per_mille > 0);
+    const float zt = logit_threshold(P->threshold);
     for (int64_t i = 0; i < n; i++) flag[i] = 1;  /* all unprocessed */
+    if (track)
+        for (int64_t i = 0; i < n; i++) {
+            L->own[i] = L->adv[i] = 0;
+            L->moved_at[i] = -1;
+            L->nm_prev[i] = L->nm_cur[i] = 0;
+        }
+    int sweep_next = 1;
+    float f[OG_MLP_IN];
     for (int32_t t = 0; t < P->max_iterations; t++) {
         i128 S = 0;
-        int64_t moves = 0;
+        int64_t moves = 0, positive = 0;
         if (!P->prune)
             for (int64_t i = 0; i < n; i++) flag[i] = 1;
+        int sweep = 0;
+        if (learned) {
+            sweep = sweep_next;
+            if (!sweep) {
+                int64_t kept = 0;
+                for (int64_t i = 0; i < n && !kept; i++) {
+                    if (!flag[i]) continue;
+                    features(g, K, L, i, pass, t, f);
+                    if (oracle_mlp_logit(P->mlp, f) >= zt) kept++;
+                }
+                if (!kept) sweep = 1;
+            }
+            if (sweep) {
+                for (int64_t i = 0; i < n; i++) flag[i] = 1;
+                st->sweeps++;
+            }
+        }
+        /* features are formed for vertices the MLP filters or the sampler records */
+        const int need_f = !sweep && t > 0 && (learned || (sm_cb && P->sample_per_mille > 0));
         if (P->mode == 0) {
             /* ASYNC: in place, ascending vertex order. */
             for (int64_t i = 0; i < n; i++) {
                 if (!flag[i]) continue;
                 flag[i] = 0;
+                if (need_f) features(g, K, L, i, pass, t, f);
+                if (learned && !sweep && oracle_mlp_logit(P->mlp, f) < zt) { st->pruned++; continue; }
                 int32_t d;
                 i128 gain;
-                if (!best_move(g, W, C, Sig, K, i, s, &d, &gain) || gain <= 0) continue;
-                int32_t c = C[i];
-                Sig[c] -= K[i];
-                Sig[d] += K[i];
-                C[i] = d;
-                S += gain;
-                moves++;
-                for (int64_t e = g->off[i]; e < g->off[i + 1]; e++)
-                    if (g->idx[e] != i) flag[g->idx[e]] = 1;
+                int64_t kic, kid;
+                int found = best_move(g, W, C, Sig, K, i, s, &d, &gain, &kic, &kid);
+                if (track) note_evaluation(L, i, found, kic, kid);
+                if (found && gain > 0) positive++;
+                int moved = found && gain > 0;
+                if (moved) {
+                    int32_t c = C[i];
+                    Sig[c] -= K[i];
+                    Sig[d] += K[i];
+                    C[i] = d;
+                    S += gain;
+                    moves++;
+                    for (int64_t e = g->off[i]; e < g->off[i + 1]; e++)
+                        if (g->idx[e] != i) flag[g->idx[e]] = 1;
+                    if (track) note_move(g, L, i, t);
+                }
+                if (need_f && sm_cb && sample_selected(i, pass, t, P->sample_per_mille))
+                    sm_cb(user, pass, t, i, f, moved);
             }
         } else {
             /* SYNC: decide against the snapshot, then apply together. */
@@ -225,12 +406,22 @@ static int32_t local_move(const og_graph* g, int64_t W, int32_t* C, int64_t* Sig
             for (int64_t i = 0; i < n; i++) {
                 dec[i] = C[i];
                 if (!flag[i]) continue;
+                if (need_f) features(g, K, L, i, pass, t, f);
+                if (learned && !sweep && oracle_mlp_logit(P->mlp, f) < zt) { st->pruned++; continue; }
                 int32_t d;
                 i128 gain;
-                if (!best_move(g, W, C, Sig, K, i, s, &d, &gain) || gain <= 0) continue;
-                if (pl && d > C[i]) continue;  /* Pick-Less rejects a larger id */
-                dec[i] = d;
-                gains[i] = gain;
+                int64_t kic, kid;
+                int found = best_move(g, W, C, Sig, K, i, s, &d, &gain, &kic, &kid);
+                if (track) note_evaluation(L, i, found, kic, kid);
+                int take = found && gain > 0;
+                if (take) positive++;
+                if (take && pl && d > C[i]) take = 0;  /* Pick-Less rejects a larger id */
+                if (take) {
+                    dec[i] = d;
+                    gains[i] = gain;
+                }
+                if (need_f && sm_cb && sample_selected(i, pass, t, P->sample_per_mille))
+                    sm_cb(user, pass, t, i, f, take);
             }
             for (int64_t i = 0; i < n; i++) flag[i] = 0;
             for (int64_t i = 0; i < n; i++) {
@@ -241,13 +432,22 @@ static int32_t local_move(const og_graph* g, int64_t W, int32_t* C, int64_t* Sig
                 moves++;
                 for (int64_t e = g->off[i]; e < g->off[i + 1]; e++)
                     if (g->idx[e] != i) flag[g->idx[e]] = 1;
+                if (track) note_move(g, L, i, t);
             }
             for (int64_t i = 0; i < n; i++) C[i] = dec[i];
         }
+        if (track)
+            for (int64_t i = 0; i < n; i++) { L->nm_prev[i] = L->nm_cur[i]; L->nm_cur[i] = 0; }
         st->iterations++;
         st->moves += moves;
         if (it_cb) it_cb(user, pass, t, n, C, Sig, moves, (int64_t)(S >> 64), (uint64_t)S);
-        if (converged(S, W, P, pass)) return t + 1;
+        int conv = converged(S, W, P, pass);
+        if (learned) {
+            if (sweep && (P->guard_tolerance ? conv : positive == 0)) return t + 1;
+            sweep_next = !sweep && conv;
+        } else if (conv) {
+            return t + 1;
+        }
     }
     return P->max_iterations;
 }
@@ -343,8 +543,9 @@ static int64_t renumber(int64_t n, int32_t* C, int32_t* map) {
  * Louvain (Algorithm 1 / Algorithm 4).  Writes the final membership of the
  * input's n vertices (dense ids, numbered by ascending final label) to memb.
  */
-int oracle_louvain(int64_t n, const int64_t* off, const int32_t* idx, const int64_t* w, const og_params* P,
-                   int32_t* memb, og_stats* st, og_iter_fn it_cb, og_pass_fn pass_cb, void* user) {
+int oracle_louvain_samples(int64_t n, const int64_t* off, const int32_t* idx, const int64_t* w,
+                           const og_params* P, int32_t* memb, og_stats* st, og_iter_fn it_cb, og_pass_fn pass_cb,
+                           og_sample_fn sm_cb, void* user) {
     memset(st, 0, sizeof(*st));
     int64_t n0 = n;
     for (int64_t v = 0; v < n0; v++) memb[v] = (int32_t)v;
@@ -361,6 +562,14 @@ int oracle_louvain(int64_t n, const int64_t* off, const int32_t* idx, const int6
     s.acc = (int64_t*)calloc(nn, sizeof(int64_t));
     s.touched = (int32_t*)malloc(nn * sizeof(int32_t));
     if (!K || !Sig || !Cp || !dec || !map || !flag || !gains || !s.acc || !s.touched) return -1;
+    if (P->prune == 2 && !P->mlp) return -2;
+    learn_state L;
+    L.own = (int64_t*)malloc(nn * sizeof(int64_t));
+    L.adv = (int64_t*)malloc(nn * sizeof(int64_t));
+    L.moved_at = (int32_t*)malloc(nn * sizeof(int32_t));
+    L.nm_prev = (int32_t*)malloc(nn * sizeof(int32_t));
+    L.nm_cur = (int32_t*)malloc(nn * sizeof(int32_t));
+    if (!L.own || !L.adv || !L.moved_at || !L.nm_prev || !L.nm_cur) return -1;
 
     og_graph g = {n0, off, idx, w};
     int64_t *own_off = NULL, *own_w = NULL;
@@ -372,7 +581,7 @@ int oracle_louvain(int64_t n, const int64_t* off, const int32_t* idx, const int6
         int64_t nc = g.n;
         vertex_weights(&g, K);
         for (int64_t i = 0; i < nc; i++) { Sig[i] = K[i]; Cp[i] = (int32_t)i; }
-        int32_t li = local_move(&g, W, Cp, Sig, K, P, p, &s, flag, dec, gains, st, it_cb, user);
+        int32_t li = local_move(&g, W, Cp, Sig, K, P, p, &s, flag, dec, gains, &L, st, it_cb, sm_cb, user);
         st->passes++;
         stopped_before_aggregate = 1;
         if (li <= 1) break;  /* globally converged */
@@ -401,7 +610,25 @@ int oracle_louvain(int64_t n, const int64_t* off, const int32_t* idx, const int6
     free(own_off); free(own_idx); free(own_w);
     free(K); free(Sig); free(Cp); free(dec); free(map); free(flag); free(gains);
     free(s.acc); free(s.touched);
+    free(L.own); free(L.adv); free(L.moved_at); free(L.nm_prev); free(L.nm_cur);
     return 0;
+}
+
+int oracle_louvain(int64_t n, const int64_t* off, const int32_t* idx, const int64_t* w, const og_params* P,
+                   int32_t* memb, og_stats* st, og_iter_fn it_cb, og_pass_fn pass_cb, void* user) {
+    return oracle_louvain_samples(n, off, idx, w, P, memb, st, it_cb, pass_cb, NULL, user);
+}
+
+/* The eight features of vertex v computed from a given state, for tests:
+ * deg, K_v, own, adv, nm (moved neighbours), moved_last (0/1), pass, t. */
+void oracle_features(int64_t deg, int64_t Kv, int64_t own, int64_t adv, int32_t nm, int32_t moved_last,
+                     int32_t pass, int32_t t, float* f) {
+    int64_t off2[2] = {0, deg};
+    og_graph g = {1, off2, NULL, NULL};
+    int64_t K1[1] = {Kv}, o1[1] = {own}, a1[1] = {adv};
+    int32_t m1[1] = {moved_last ? t - 1 : -1}, n1[1] = {nm}, z1[1] = {0};
+    learn_state L = {o1, a1, m1, n1, z1};
+    features(&g, K1, &L, 0, pass, t, f);
 }
 
 /* ------------------------------------------------- single-vertex helpers */
