@@ -76,8 +76,9 @@ typedef struct {
 /* Per-iteration trace: state after the iteration's moves are applied. */
 typedef void (*og_iter_fn)(void* user, int32_t pass, int32_t iter, int64_t n, const int32_t* cprime,
                            const int64_t* sigma, int64_t moves, int64_t gain_hi, uint64_t gain_lo);
-/* Training sample: features of an evaluated vertex before the iteration and
- * whether it then moved. */
+/* Training sample: features of an evaluated vertex with at least one arc,
+ * before the iteration, and whether it then moved.  Sweeps and iteration 0
+ * record none. */
 typedef void (*og_sample_fn)(void* user, int32_t pass, int32_t iter, int64_t v, const float* feat, int32_t label);
 /* Per-pass trace: the super-vertex graph produced by aggregation. */
 typedef void (*og_pass_fn)(void* user, int32_t pass, int64_t n, const int64_t* off, const int32_t* idx,
@@ -397,7 +398,7 @@ static int32_t local_move(const og_graph* g, int64_t W, int32_t* C, int64_t* Sig
                         if (g->idx[e] != i) flag[g->idx[e]] = 1;
                     if (track) note_move(g, L, i, t);
                 }
-                if (need_f && sm_cb && sample_selected(i, pass, t, P->sample_per_mille))
+                if (need_f && sm_cb && g->off[i + 1] > g->off[i] && sample_selected(i, pass, t, P->sample_per_mille))
                     sm_cb(user, pass, t, i, f, moved);
             }
         } else {
@@ -420,7 +421,7 @@ static int32_t local_move(const og_graph* g, int64_t W, int32_t* C, int64_t* Sig
                     dec[i] = d;
                     gains[i] = gain;
                 }
-                if (need_f && sm_cb && sample_selected(i, pass, t, P->sample_per_mille))
+                if (need_f && sm_cb && g->off[i + 1] > g->off[i] && sample_selected(i, pass, t, P->sample_per_mille))
                     sm_cb(user, pass, t, i, f, take);
             }
             for (int64_t i = 0; i < n; i++) flag[i] = 0;
