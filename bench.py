@@ -8,6 +8,10 @@ Pick-Less every 4, vertex pruning), ASYNC local moving.
 
 One step = one complete louvain_run on the device-resident graph.  The
 metric counts stored arcs (each undirected edge twice), as the paper does.
+The timed steps run without per-kernel events; the same number of steps is
+then repeated with HIP events around every launch for the roofline figures.
+A second leg trains the learned move-pruner on samples recorded from
+separate R-MAT graphs (seeds 1018-1020) and times the same workload with it.
 Prints one JSON line.
 """
 import argparse
@@ -20,6 +24,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "move_fused_rmat22_traffic.md")
+TRAFFIC_SOURCES = ["paper_2501_19004_amd/csrc/lv_move.hip", "paper_2501_19004_amd/csrc/lv_common.h",
+                   "paper_2501_19004_amd/csrc/lv_internal.h"]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when the summary is missing or the kernel sources changed since."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != kernel_source_digest():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def make_graph(name):
@@ -36,6 +73,59 @@ def make_graph(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def timed_runs(L, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        L.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        L.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / max(steps, 1)
+    q, _, _ = L.modularity()
+    return dt, q, L.stats()
+
+
+def learned_leg(lv, torch, g, off, idx, w, mode, args, q_plain, dt_plain):
+    """Train the pruner MLP on samples recorded (flag pruning) from R-MAT
+    scale 18 graphs with seeds 1018-1020, then time the workload with it."""
+    import graphgen as gg
+    t0 = time.time()
+    bufs = []
+    for seed in (1018, 1019, 1020):
+        tg = gg.rmat(18, 16, seed=seed)
+        o2, i2, w2 = lv.graph_tensors(tg, "cuda:0")
+        T = lv.Louvain(o2, i2, w2, mode=mode)
+        buf = T.collect_samples(2_000_000, 250)
+        T.run()
+        bufs.append(buf[:T.sample_count()].clone())
+        T.close()
+    S = torch.cat(bufs)
+    pos = float(S[:, 8].mean().item())
+    wts = lv.pruner_init(1018, "cuda:0")
+    loss0, _ = lv.pruner_loss_grad(wts, S, 1.0)
+    loss = lv.pruner_train(wts, S, steps=1500, batch=4096, lr=3e-3, pos_weight=1.0, seed=1018)
+    t_train = time.time() - t0
+    print(f"[bench] pruner: {S.shape[0]} samples ({pos:.3f} moved), loss {loss0:.4f} -> {loss:.4f}, "
+          f"{t_train:.1f}s", file=sys.stderr, flush=True)
+    L = lv.Louvain(off, idx, w, mode=mode, pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
+                   pruner_threshold=args.threshold, async_coherent=args.async_coherent)
+    dt, q, st = timed_runs(L, args.steps, args.warmup)
+    L.close()
+    print(f"[bench] learned: {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), sweeps={st.sweeps} "
+          f"pruned={st.pruned} iterations={st.iterations}", file=sys.stderr, flush=True)
+    return {"value": round(g.nnz / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
+            "speedup_vs_plain": round(dt_plain / dt, 3), "modularity": round(q, 6),
+            "dq_vs_plain": round(q - q_plain, 6), "equal_modularity": abs(q - q_plain) <= 0.002,
+            "threshold": args.threshold, "guard": "tolerance", "passes": st.passes, "iterations": st.iterations,
+            "sweeps": st.sweeps, "pruned": st.pruned, "vertices_evaluated": st.vertices_evaluated,
+            "arcs_scanned": st.arcs_scanned,
+            "training": {"graphs": "R-MAT scale 18, edge factor 16, seeds 1018-1020", "samples": int(S.shape[0]),
+                         "positive_rate": round(pos, 4), "loss_initial": round(loss0, 5), "loss_final": round(loss, 5),
+                         "steps": 1500, "batch": 4096, "lr": 3e-3, "seconds": round(t_train, 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +136,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-pruner leg")
+    ap.add_argument("--threshold", type=float, default=0.5, help="learned pruner: keep iff sigmoid >= threshold")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (counter calibration run) and exit")
+    ap.add_argument("--async-coherent", type=int, default=1, choices=[0, 1],
+                    help="ASYNC: device-coherent loads of C' and Sigma' (1) or cached loads (0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -59,29 +155,33 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": nb, "source_digest": kernel_source_digest()}))
+        return
     t0 = time.time()
     g, desc = make_graph(args.workload)
     print(f"[bench] generated {desc}: n={g.n} arcs={g.nnz} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     off, idx, w = lv.graph_tensors(g, "cuda:0")
     mode = lv.ASYNC if args.mode == "async" else lv.SYNC
-    L = lv.Louvain(off, idx, w, mode=mode)
-    for _ in range(args.warmup):
-        L.run()
-    if not args.no_profile:
-        L.set_profiling(True)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(args.steps):
-        L.run()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / max(args.steps, 1)
-    st = L.stats()
-    q, num, den = L.modularity()
+    L = lv.Louvain(off, idx, w, mode=mode, async_coherent=args.async_coherent)
+    dt, q, st = timed_runs(L, args.steps, args.warmup)
     print(f"[bench] {args.steps} runs, {dt * 1e3:.2f} ms/run, Q={q:.5f}, passes={st.passes} "
           f"iterations={st.iterations} communities={st.communities}", file=sys.stderr, flush=True)
+    kstats = []
+    if not args.no_profile:
+        L.set_profiling(True)
+        dtp, _, _ = timed_runs(L, args.steps, 0)
+        kstats = L.kernel_stats()
+        L.set_profiling(False)
+        print(f"[bench] {args.steps} event-timed runs, {dtp * 1e3:.2f} ms/run", file=sys.stderr, flush=True)
 
     roofline = None
-    kstats = L.kernel_stats() if not args.no_profile else []
     if kstats:
         if args.kernels:
             for k in kstats:
@@ -97,11 +197,17 @@ def main():
             tot_ms = sum(k["ms"] for k in moves)
             tot_b = sum(k["alg_bytes"] for k in moves)
             roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
-                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                        "traffic": measured_traffic() if dom["name"] == "move_b0_3" else None,
+                        "event_timed_ms_per_step": round(dtp * 1e3, 3),
                         "avg_launch_us": round(ms_launch * 1e3, 2),
                         "alg_bytes_per_launch": int(bytes_launch),
                         "local_move_phase_GBs": round(tot_b / (tot_ms * 1e-3) / 1e9, 1) if tot_ms else None,
                         "local_move_ms_per_run": round(tot_ms / args.steps, 3)}
+
+    learned = None
+    if not args.no_learned:
+        learned = learned_leg(lv, torch, g, off, idx, w, mode, args, q, dt)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -131,11 +237,13 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "vertices": g.n, "arcs": g.nnz, "undirected_edges": g.nnz // 2,
-                   "mode": args.mode, "pruner": "flags", "modularity": round(q, 6), "passes": st.passes,
+                   "mode": args.mode, "pruner": "flags", "async_coherent": args.async_coherent, "modularity": round(q, 6), "passes": st.passes,
                    "iterations": st.iterations, "communities": st.communities,
+                   "vertices_evaluated": st.vertices_evaluated, "arcs_scanned": st.arcs_scanned,
                    "undirected_Medges_per_s": round(g.nnz / 2 / dt / 1e6, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_pruner": learned,
     }
     print(json.dumps(out))
     L.close()

@@ -55,9 +55,39 @@ typedef enum { LOUVAIN_ASYNC = 0, LOUVAIN_SYNC = 1 } louvain_mode;
 /* Which vertices an iteration evaluates.
  * NONE: all vertices every iteration.
  * FLAGS: vertex pruning (Section 4.1, "Vertex pruning"): a vertex is evaluated
- *   again only after a neighbour changed community. */
-typedef enum { LOUVAIN_PRUNE_NONE = 0, LOUVAIN_PRUNE_FLAGS = 1 } louvain_pruner;
+ *   again only after a neighbour changed community.
+ * LEARNED: FLAGS, with each flagged vertex further filtered by the pruner MLP
+ *   below, and a sweep guard: iteration 0 of a pass evaluates every vertex, so
+ *   does an iteration whose filtered queue is empty and the iteration after a
+ *   non-sweep iteration that passes the tolerance test; a pass ends only at
+ *   such a sweep that passes the exit test (guard_tolerance = 0: no evaluated
+ *   vertex had a positive best gain, before Pick-Less; 1: the tolerance test)
+ *   or at max_iterations. */
+typedef enum { LOUVAIN_PRUNE_NONE = 0, LOUVAIN_PRUNE_FLAGS = 1, LOUVAIN_PRUNE_LEARNED = 2 } louvain_pruner;
 
+/* Learned move-pruner: an MLP 8 -> 32 -> 32 -> 1 with ReLU hidden layers, in
+ * FP32.  Weight layout (LOUVAIN_MLP_PARAMS floats): W1[32][8], b1[32],
+ * W2[32][32], b2[32], w3[32], b3.  Each neuron starts at its bias and adds
+ * its inputs in index order by fused multiply-adds (a fully specified FP32
+ * result).  A flagged vertex is evaluated iff the output logit z satisfies
+ * z >= log(theta / (1 - theta)), i.e. sigmoid(z) >= theta = pruner_threshold
+ * (theta <= 0 keeps all, theta >= 1 none).  Features of vertex v of the
+ * current level at the start of iteration t of pass p, all FP32 from integers:
+ *   f0 = mlog2(1 + deg v) / 16        f1 = own_v / K_v
+ *   f2 = mlog2(1 + m_v) / 16          f3 = m_v / deg v
+ *   f4 = 1 if v moved in t - 1, else 0
+ *   f5 = p / 10                       f6 = t / 20
+ *   f7 = adv_v / K_v
+ * deg v = row length; m_v = neighbours j != v that moved in iteration t - 1;
+ * own_v = K_{v->C'[v]} and adv_v = K_{v->d*} - K_{v->C'[v]} (d* = best
+ * candidate, K_{v->d*} = 0 without one), both as of v's last evaluation in
+ * the pass (0 before it); a ratio with a zero denominator is 0;
+ * mlog2(x) = e + (x - 2^e) / 2^e with e = floor(log2 x) (Mitchell's
+ * piecewise-linear logarithm). */
+#define LOUVAIN_MLP_IN 8
+#define LOUVAIN_MLP_HIDDEN 32
+#define LOUVAIN_MLP_PARAMS (32 * 8 + 32 + 32 * 32 + 32 + 32 + 1)
+#define LOUVAIN_SAMPLE_FLOATS 9 /* 8 features + label (1 = moved) */
 
 /* Input graph.  offsets: device, n+1 entries of int32 (offset_bits = 32) or
  * int64 (offset_bits = 64), offsets[0] = 0, non-decreasing, offsets[n] = nnz.
@@ -109,7 +139,11 @@ typedef struct {
     /* ASYNC only: apply async_slices to the first this-many iterations of
      * every pass (0 = to every iteration). */
     int32_t async_slice_iters;
-    int32_t reserved[4];
+    /* LEARNED pruner only: exit test of a sweep (0 strict, 1 tolerance). */
+    int32_t guard_tolerance;
+    int32_t reserved[3];
+    const float* pruner_weights; /* LEARNED: device, LOUVAIN_MLP_PARAMS floats, read during louvain_run */
+    double pruner_threshold;     /* LEARNED: theta */
 } louvain_params;
 
 /* Per-run counters, filled by louvain_get_stats after louvain_run. */
@@ -126,6 +160,8 @@ typedef struct {
     double ms_aggregate;        /* aggregation kernels (HIP events; profile_kernels only) */
     int32_t iterations_per_pass[32];
     int64_t communities_per_pass[32];
+    int64_t sweeps;             /* LEARNED: iterations that evaluated every vertex */
+    int64_t pruned;             /* LEARNED: flagged vertices skipped by the MLP */
 } louvain_stats;
 
 /* Per-kernel timing record (profiling mode). */
@@ -197,6 +233,50 @@ louvain_status louvain_get_kernel_stats(louvain_t* h, louvain_kernel_stat* out, 
 /* Install trace callbacks (either may be NULL).  Tracing copies state to the
  * host after every iteration and pass; it is for testing, not speed. */
 louvain_status louvain_set_trace(louvain_t* h, louvain_iter_fn iter_fn, louvain_pass_fn pass_fn, void* user);
+
+/* Record pruner training samples during later runs of h (any mode and
+ * pruner): in every iteration t >= 1 that is not a sweep, each vertex v of the
+ * iteration's queue with splitmix64(v + 2^32 (p 2^16 + t)) mod 1000 <
+ * sample_per_mille (splitmix64: the SplitMix64 output function of one
+ * counter value) yields LOUVAIN_SAMPLE_FLOATS floats: its 8 features and the
+ * label 1 if v moved in iteration t, else 0.  Samples are appended in no
+ * particular order.  buffer: device, capacity * LOUVAIN_SAMPLE_FLOATS floats,
+ * borrowed until the next call (buffer = NULL or sample_per_mille = 0
+ * disables).  Samples beyond capacity are dropped; the count is reset at the
+ * start of every louvain_run.  louvain_sample_count: samples written by the
+ * last run (at most capacity). */
+louvain_status louvain_collect_samples(louvain_t* h, float* buffer, int64_t capacity, int32_t sample_per_mille);
+louvain_status louvain_sample_count(louvain_t* h, int64_t* count);
+
+/* Pruner MLP on its own (no handle).  Pointers are device memory; work is
+ * enqueued on `stream` and the calls return after it completes.  Errors:
+ * LOUVAIN_ERR_INVALID for bad arguments, LOUVAIN_ERR_HIP for runtime failures
+ * (message in louvain_last_error(NULL)).
+ * louvain_pruner_init: Glorot-uniform weights, zero biases: parameter k of
+ *   the flat layout draws u = (splitmix64(seed + k * 0x9E3779B97F4A7C15) >> 40)
+ *   / 2^24 and becomes (2u - 1) * sqrt(6 / (fan_in + fan_out)) in FP32.
+ * louvain_pruner_predict: logit[k] = MLP(features[8k .. 8k+7]) (FP32, the
+ *   fused order above).
+ * louvain_pruner_loss_grad: samples as recorded (8 features + label); loss =
+ *   (1/N) sum_k c_k (softplus(z_k) - y_k z_k) with c_k = pos_weight for
+ *   y_k = 1, else 1; grad (LOUVAIN_MLP_PARAMS floats) is overwritten with its
+ *   gradient, *loss receives the loss.
+ * louvain_pruner_train: `steps` Adam updates (Kingma and Ba; beta1 0.9,
+ *   beta2 0.999, eps 1e-8, learning rate lr) of the same loss on mini-batches:
+ *   slot j of step s uses sample splitmix64(seed + (s * batch + j) *
+ *   0x9E3779B97F4A7C15) mod count (all samples, in order, when batch >=
+ *   count).  scratch: louvain_pruner_scratch_floats(batch) floats of device
+ *   memory (Adam moments, gradient); *last_loss receives the loss of the last
+ *   mini-batch before its update. */
+louvain_status louvain_pruner_init(float* weights, uint64_t seed, void* stream);
+louvain_status louvain_pruner_predict(const float* weights, const float* features, int64_t count, float* logit,
+                                      void* stream);
+louvain_status louvain_pruner_loss_grad(const float* weights, const float* samples, int64_t count,
+                                        float pos_weight, float* grad, double* loss, void* stream);
+int64_t louvain_pruner_scratch_floats(int32_t batch);
+louvain_status louvain_pruner_train(float* weights, const float* samples, int64_t count, int32_t steps,
+                                    int32_t batch, float lr, float pos_weight, uint64_t seed, float* scratch,
+                                    double* last_loss, void* stream);
 
 /* Last error message of h (or of the last failed create when h is NULL).
  * Never NULL; valid until the next call on h. */

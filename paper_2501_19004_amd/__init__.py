@@ -25,10 +25,15 @@ ASYNC = 0
 SYNC = 1
 PRUNE_NONE = 0
 PRUNE_FLAGS = 1
+PRUNE_LEARNED = 2
+MLP_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1
+SAMPLE_FLOATS = 9
 
 EXPORTED = ["louvain_params_default", "louvain_workspace_size", "louvain_create", "louvain_run",
             "louvain_get_membership", "louvain_modularity", "louvain_get_stats", "louvain_set_profiling",
-            "louvain_get_kernel_stats", "louvain_set_trace", "louvain_last_error", "louvain_destroy"]
+            "louvain_get_kernel_stats", "louvain_set_trace", "louvain_last_error", "louvain_destroy",
+            "louvain_collect_samples", "louvain_sample_count", "louvain_pruner_init", "louvain_pruner_predict",
+            "louvain_pruner_loss_grad", "louvain_pruner_scratch_floats", "louvain_pruner_train"]
 
 
 class LouvainGraph(ctypes.Structure):
@@ -44,7 +49,8 @@ class LouvainParams(ctypes.Structure):
                 ("bucket_max_degree", ctypes.c_int32 * 8), ("agg_bucket_max", ctypes.c_int32 * 8),
                 ("async_coherent", ctypes.c_int32), ("bucket_order", ctypes.c_int32),
                 ("async_slices", ctypes.c_int32), ("async_slice_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("guard_tolerance", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("pruner_weights", ctypes.c_void_p), ("pruner_threshold", ctypes.c_double)]
 
 
 class LouvainStats(ctypes.Structure):
@@ -52,7 +58,8 @@ class LouvainStats(ctypes.Structure):
                 ("communities", ctypes.c_int64), ("vertices_evaluated", ctypes.c_int64),
                 ("arcs_scanned", ctypes.c_int64), ("distinct_scanned", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("ms_move", ctypes.c_double), ("ms_aggregate", ctypes.c_double),
-                ("iterations_per_pass", ctypes.c_int32 * 32), ("communities_per_pass", ctypes.c_int64 * 32)]
+                ("iterations_per_pass", ctypes.c_int32 * 32), ("communities_per_pass", ctypes.c_int64 * 32),
+                ("sweeps", ctypes.c_int64), ("pruned", ctypes.c_int64)]
 
 
 class LouvainKernelStat(ctypes.Structure):
@@ -105,6 +112,22 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_last_error.argtypes = [vp]
     lib.louvain_destroy.restype = None
     lib.louvain_destroy.argtypes = [vp]
+    lib.louvain_collect_samples.restype = ctypes.c_int
+    lib.louvain_collect_samples.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32]
+    lib.louvain_sample_count.restype = ctypes.c_int
+    lib.louvain_sample_count.argtypes = [vp, _I64P]
+    lib.louvain_pruner_init.restype = ctypes.c_int
+    lib.louvain_pruner_init.argtypes = [vp, ctypes.c_uint64, vp]
+    lib.louvain_pruner_predict.restype = ctypes.c_int
+    lib.louvain_pruner_predict.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    lib.louvain_pruner_loss_grad.restype = ctypes.c_int
+    lib.louvain_pruner_loss_grad.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_float, vp,
+                                             ctypes.POINTER(ctypes.c_double), vp]
+    lib.louvain_pruner_scratch_floats.restype = ctypes.c_int64
+    lib.louvain_pruner_scratch_floats.argtypes = [ctypes.c_int32]
+    lib.louvain_pruner_train.restype = ctypes.c_int
+    lib.louvain_pruner_train.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_double), vp]
     _lib = lib
     return lib
 
@@ -189,6 +212,44 @@ def louvain_last_error(h=None) -> str:
     return msg.decode() if msg else ""
 
 
+def louvain_collect_samples(h, buffer_ptr: int, capacity: int, sample_per_mille: int) -> None:
+    _check(load_library().louvain_collect_samples(h, buffer_ptr or None, capacity, sample_per_mille), h)
+
+
+def louvain_sample_count(h) -> int:
+    c = ctypes.c_int64()
+    _check(load_library().louvain_sample_count(h, ctypes.byref(c)), h)
+    return int(c.value)
+
+
+def louvain_pruner_init(weights_ptr: int, seed: int, stream: int) -> None:
+    _check(load_library().louvain_pruner_init(weights_ptr, seed, stream))
+
+
+def louvain_pruner_predict(weights_ptr: int, features_ptr: int, count: int, logit_ptr: int, stream: int) -> None:
+    _check(load_library().louvain_pruner_predict(weights_ptr, features_ptr, count, logit_ptr, stream))
+
+
+def louvain_pruner_loss_grad(weights_ptr: int, samples_ptr: int, count: int, pos_weight: float, grad_ptr: int,
+                             stream: int) -> float:
+    loss = ctypes.c_double()
+    _check(load_library().louvain_pruner_loss_grad(weights_ptr, samples_ptr, count, pos_weight, grad_ptr,
+                                                   ctypes.byref(loss), stream))
+    return float(loss.value)
+
+
+def louvain_pruner_scratch_floats(batch: int) -> int:
+    return int(load_library().louvain_pruner_scratch_floats(batch))
+
+
+def louvain_pruner_train(weights_ptr: int, samples_ptr: int, count: int, steps: int, batch: int, lr: float,
+                         pos_weight: float, seed: int, scratch_ptr: int, stream: int) -> float:
+    loss = ctypes.c_double()
+    _check(load_library().louvain_pruner_train(weights_ptr, samples_ptr, count, steps, batch, lr, pos_weight, seed,
+                                               scratch_ptr, ctypes.byref(loss), stream))
+    return float(loss.value)
+
+
 def louvain_destroy(h) -> None:
     if h:
         load_library().louvain_destroy(h)
@@ -209,10 +270,15 @@ class Louvain:
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU available: the Louvain library runs only on the GPU")
         load_library()
-        self._keep = (offsets, indices, weights)
+        self._keep = (offsets, indices, weights, overrides.get("pruner_weights"))
         self.params = params or louvain_params_default()
         for k, v in overrides.items():
-            if k in ("bucket_max_degree", "agg_bucket_max"):
+            if k == "pruner_weights":
+                if v is not None and (v.dtype != torch.float32 or v.numel() != MLP_PARAMS or not v.is_cuda
+                                      or not v.is_contiguous()):
+                    raise ValueError(f"pruner_weights must be a contiguous float32 GPU tensor of {MLP_PARAMS}")
+                self.params.pruner_weights = v.data_ptr() if v is not None else None
+            elif k in ("bucket_max_degree", "agg_bucket_max"):
                 arr = getattr(self.params, k)
                 for i, x in enumerate(v):
                     arr[i] = x
@@ -279,6 +345,19 @@ class Louvain:
         self._cb = (ITER_FN(it), PASS_FN(pa))
         louvain_set_trace(self.h, self._cb[0], self._cb[1])
 
+    def collect_samples(self, capacity: int, sample_per_mille: int):
+        """Record training samples during later runs into a new float32
+        tensor [capacity, SAMPLE_FLOATS]; returns it (rows filled up to
+        sample_count())."""
+        import torch
+        buf = torch.zeros((max(capacity, 1), SAMPLE_FLOATS), dtype=torch.float32, device=self.workspace.device)
+        self._samples = buf
+        louvain_collect_samples(self.h, buf.data_ptr(), capacity, sample_per_mille)
+        return buf
+
+    def sample_count(self) -> int:
+        return louvain_sample_count(self.h)
+
     def close(self):
         if getattr(self, "h", None):
             louvain_destroy(self.h)
@@ -300,3 +379,47 @@ def graph_tensors(g, device="cuda", offset_bits: int = 32, unit_weights: bool | 
     unit = bool(unit_weights) if unit_weights is not None else bool(g.weights.size == 0 or g.weights.max() == 1)
     w = None if unit else torch.from_numpy(np.ascontiguousarray(g.weights, dtype=np.int32)).to(device)
     return off.to(device), idx.to(device), w
+
+
+# ------------------------------------------------------------ pruner MLP
+
+def _stream_of(t):
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def pruner_init(seed: int, device="cuda"):
+    """Glorot-uniform pruner weights as a float32 tensor [MLP_PARAMS]."""
+    import torch
+    w = torch.empty(MLP_PARAMS, dtype=torch.float32, device=device)
+    louvain_pruner_init(w.data_ptr(), seed, _stream_of(w))
+    return w
+
+
+def pruner_predict(weights, features):
+    """Output logits of the pruner MLP for features [k, 8] (float32, GPU)."""
+    import torch
+    x = features.contiguous()
+    out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    louvain_pruner_predict(weights.data_ptr(), x.data_ptr(), x.shape[0], out.data_ptr(), _stream_of(x))
+    return out
+
+
+def pruner_loss_grad(weights, samples, pos_weight: float = 1.0):
+    """(loss, gradient tensor) of the weighted cross-entropy over samples [k, 9]."""
+    import torch
+    s = samples.contiguous()
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=s.device)
+    loss = louvain_pruner_loss_grad(weights.data_ptr(), s.data_ptr(), s.shape[0], pos_weight, g.data_ptr(),
+                                    _stream_of(s))
+    return loss, g
+
+
+def pruner_train(weights, samples, steps: int, batch: int = 4096, lr: float = 1e-3, pos_weight: float = 1.0,
+                 seed: int = 0) -> float:
+    """Adam training of weights (updated in place); returns the last loss."""
+    import torch
+    s = samples.contiguous()
+    scratch = torch.empty(louvain_pruner_scratch_floats(batch), dtype=torch.float32, device=s.device)
+    return louvain_pruner_train(weights.data_ptr(), s.data_ptr(), s.shape[0], steps, batch, lr, pos_weight, seed,
+                                scratch.data_ptr(), _stream_of(s))

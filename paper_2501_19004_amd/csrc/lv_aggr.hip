@@ -174,10 +174,30 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_aggregate_lds(Graph<OffT,
                                     [&](int32_t d, AccT w) {
                                         table_add<AccT>(keys, vals, CAP - 1, hash_slot<L2C>(d), d, w);
                                     });
-    i64 L = 0;
-    for (int s = lane; s < CAP; s += G) L += keys[s] != EMPTY_KEY;
-    L = group_sum<G>(L, s_t);
-    bitonic_sort_group<G, AccT>(keys, vals, CAP, lane);
+    // Move the occupied slots to the front, then sort only the next power of
+    // two above their count (the rest of the table stays empty).
+    constexpr int PER = CAP / G;
+    int32_t rk[PER];
+    AccT rv[PER];
+    i64 mine = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        rk[q] = keys[lane + q * G];
+        rv[q] = vals[lane + q * G];
+        mine += rk[q] != EMPTY_KEY;
+    }
+    const i64 incl = group_incl_scan<G>(mine, s_t);
+    const i64 L = group_sum<G>(mine, s_t);
+    group_sync<G>();
+    i64 at = incl - mine;
+#pragma unroll
+    for (int q = 0; q < PER; q++)
+        if (rk[q] != EMPTY_KEY) { keys[at] = rk[q]; vals[at] = rv[q]; at++; }
+    int64_t P = 1;
+    while (P < L) P <<= 1;
+    for (i64 x = L + lane; x < P; x += G) { keys[x] = EMPTY_KEY; vals[x] = 0; }
+    group_sync<G>();
+    bitonic_sort_group<G, AccT>(keys, vals, P, lane);
     if (active) {
         const i64 h = a.hoff[c];
         for (i64 x = lane; x < L; x += G) {
@@ -312,9 +332,13 @@ __global__ void __launch_bounds__(1024) k_big_insert(Graph<OffT, WK> g, BigArgs 
     const int log2cap = __ffsll((long long)cap) - 1;
     int32_t* keys = a.keys + toff;
     AccT* vals = (AccT*)a.vals + toff;
+    int32_t* slots = a.slots + toff / 2;  // cap >= 2 * distinct keys
     for (int s = tid; s < BIG_LCAP; s += G) {
         const int32_t d = s_keys[s];
-        if (d != EMPTY_KEY) table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d, s_vals[s]);
+        if (d == EMPTY_KEY) continue;
+        const int64_t got = table_add_claim<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d,
+                                                  s_vals[s]);
+        if (got >= 0) slots[atomicAdd(&a.cnt[h], 1)] = (int32_t)got;
     }
 }
 
@@ -331,6 +355,8 @@ template <typename AccT>
 __global__ void __launch_bounds__(1024) k_big_extract(BigArgs a) {
     constexpr int G = 1024;
     __shared__ i64 s_t[G / WAVE];
+    __shared__ int32_t s_k[BIG_SORT_MAX];
+    __shared__ AccT s_v[BIG_SORT_MAX];
     const int tid = threadIdx.x;
     uint32_t* bm = a.bitmaps + (int64_t)blockIdx.x * a.words;
     for (int32_t h = blockIdx.x; h < a.nbig; h += gridDim.x) {
@@ -340,11 +366,40 @@ __global__ void __launch_bounds__(1024) k_big_extract(BigArgs a) {
         const int log2cap = __ffsll((long long)cap) - 1;
         const int32_t* keys = a.keys + toff;
         const AccT* vals = (const AccT*)a.vals + toff;
+        const int32_t* slots = a.slots + toff / 2;
+        const int64_t L = a.cnt[h];
+        const int64_t base = a.hoff[c];
+        if (L <= BIG_SORT_MAX) {
+            // the listed entries, padded to a power of two, sorted in LDS
+            int64_t P = 1;
+            while (P < L) P <<= 1;
+            for (int64_t k = tid; k < P; k += G) {
+                if (k < L) {
+                    const int32_t sl = slots[k];
+                    s_k[k] = keys[sl];
+                    s_v[k] = vals[sl];
+                } else {
+                    s_k[k] = EMPTY_KEY;
+                    s_v[k] = 0;
+                }
+            }
+            __syncthreads();
+            bitonic_sort_group<G, AccT>(s_k, s_v, P, tid);
+            for (int64_t x = tid; x < L; x += G) {
+                a.hidx[base + x] = s_k[x];
+                if (a.out_w64) ((i64*)a.hw)[base + x] = (i64)s_v[x];
+                else ((int32_t*)a.hw)[base + x] = (int32_t)s_v[x];
+            }
+            if (tid == 0) a.rowlen[c] = (int32_t)L;
+            __syncthreads();
+            continue;
+        }
+        // long rows: mark the keys in a bitmap over [0, ncom) and walk it in order
         for (int64_t w = tid; w < a.words; w += G) bm[w] = 0;
         __syncthreads();
-        for (int64_t s = tid; s < cap; s += G) {
-            const int32_t d = keys[s];
-            if (d != EMPTY_KEY) atomicOr(&bm[d >> 5], 1u << (d & 31));
+        for (int64_t k = tid; k < L; k += G) {
+            const int32_t d = keys[slots[k]];
+            atomicOr(&bm[d >> 5], 1u << (d & 31));
         }
         __syncthreads();
         const int64_t per = (a.words + G - 1) / G;
@@ -353,7 +408,6 @@ __global__ void __launch_bounds__(1024) k_big_extract(BigArgs a) {
         for (int64_t w = w0; w < w1; w++) cnt += __popc(bm[w]);
         const i64 incl = group_incl_scan<G>(cnt, s_t);
         i64 rank = incl - cnt;
-        const int64_t base = a.hoff[c];
         for (int64_t w = w0; w < w1; w++) {
             uint32_t bits = bm[w];
             while (bits) {

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
@@ -44,6 +45,7 @@ struct Layout {
     size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
     size_t hidx, hw, sup_off[2], sup_idx[2], sup_w[2], pool_keys, pool_vals, scan;
     size_t md, mpos, bnch, bchpre, bitmaps, gdec, blkcnt, blkoff;
+    size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots;
     int64_t bitmap_words;
     int64_t pool_entries;
     size_t total;
@@ -91,6 +93,8 @@ bool make_layout(int64_t n, int64_t m, Layout* L) {
     L->pool_entries = pool;
     L->pool_keys = take((size_t)pool * 4);
     L->pool_vals = take((size_t)pool * 8);
+    L->hslots = take((size_t)pool / 2 * 4);
+    L->hcnt = take((N + 1) * 4);
     L->scan = take(scan_scratch_bytes(n + 2));
     L->gdec = take(N * 4);
     L->blkcnt = take((size_t)(MAX_BUCKETS * (bucket_blocks(n + 1) + 1) + 8) * 4);
@@ -101,6 +105,10 @@ bool make_layout(int64_t n, int64_t m, Layout* L) {
     L->bchpre = take((N + 2) * 8);
     L->bitmap_words = (n + 32) / 32;
     L->bitmaps = take((size_t)BIG_EXTRACT_BLOCKS * (size_t)L->bitmap_words * 4);
+    L->f_own = take(N * 8);
+    L->f_adv = take(N * 8);
+    L->f_moved = take(N * 4);
+    L->f_nm = take(N * 4);
     L->total = o;
     return true;
 }
@@ -113,12 +121,12 @@ struct KRec {
 
 enum KName { K_MOVE_FUSED = 0, K_MOVE1, K_MOVE2, K_MOVE3, K_MOVE4, K_MOVE_HUB, K_SYNC_APPLY, K_PASS_INIT, K_AGG_PREP,
              K_AGG0, K_AGG1, K_AGG2, K_AGG3, K_AGG_BIG_INSERT, K_AGG_BIG_EXTRACT, K_COMPACT, K_QUEUE, K_HUB_MARK,
-             K_COUNT };
+             K_LEARN_FILTER, K_COUNT };
 const char* KNAMES[K_COUNT] = {"move_b0_3", "move_unused1", "move_unused2", "move_unused3", "move_b4", "move_hub",
                                "sync_apply",
                                "pass_init", "aggregate_prep", "aggregate_b0", "aggregate_b1", "aggregate_b2",
                                "aggregate_b3", "aggregate_big_insert", "aggregate_big_extract", "compact",
-                               "queue_build", "hub_mark"};
+                               "queue_build", "hub_mark", "learn_filter"};
 
 }  // namespace
 
@@ -150,6 +158,10 @@ struct louvain_s {
     int64_t kbytes[K_COUNT] = {};
     uint32_t stamp = 0;
     Buckets mb{}, ab{};
+    float* smp_buf = nullptr;  // training samples (borrowed)
+    int64_t smp_cap = 0;
+    int32_t smp_rate = 0;
+    int64_t smp_count = 0;
 
     template <typename T>
     T* at(size_t off) { return (T*)(ws + off); }
@@ -235,19 +247,30 @@ bool converged(unsigned __int128 S, int64_t W, const louvain_params& p, int pass
 
 // Bytes of algorithmic traffic of one evaluation batch (see the roofline model).
 int64_t move_alg_bytes(const LevelView& L, uint64_t eval, uint64_t arcs, uint64_t distinct, uint64_t moves,
-                       uint64_t marcs, int sync) {
+                       uint64_t marcs, int sync, int learn) {
     const int64_t offb = L.t.off64 ? 8 : 4;
     const int64_t wb = L.t.wk == 0 ? 0 : (L.t.wk == 1 ? 4 : 8);
     int64_t b = (int64_t)eval * (4 + 4 + 8 + 8 + 2 * offb) + (int64_t)arcs * (4 + 4 + wb) + (int64_t)distinct * 8;
     if (sync) b += (int64_t)moves * 8;
     else b += (int64_t)moves * (4 + 16) + (int64_t)marcs * (4 + 4 + 1);
+    // learned-pruner state: own/adv per evaluation, moved tag per move, a
+    // moved-neighbour count per arc of a mover
+    if (learn) b += (int64_t)eval * 16 + (int64_t)moves * 4 + (int64_t)marcs * 4;
     return b;
+}
+
+// Bytes of the learned filter: a stamp per vertex, the feature state of each
+// flagged vertex, an unstamp per dropped vertex, each recorded sample.
+int64_t filter_alg_bytes(const LevelView& L, int64_t n, int64_t flagged, int64_t dropped, int64_t samples) {
+    const int64_t offb = L.t.off64 ? 8 : 4;
+    return n * 4 + flagged * (8 + 8 + 8 + 4 + 4 + 2 * offb) + dropped * 4 + samples * 36;
 }
 
 // Sum of the striped per-iteration counters.
 struct IterTotals {
     unsigned __int128 S;
     uint64_t moves;
+    uint64_t positive;
     int32_t qcount[MAX_BUCKETS];
 };
 IterTotals sum_iter(const Ctl& c) {
@@ -255,6 +278,7 @@ IterTotals sum_iter(const Ctl& c) {
     for (int k = 0; k < STRIPES; k++) {
         t.S += ((unsigned __int128)c.s_hi[k] << 64) + (unsigned __int128)c.s_lo[k];
         t.moves += c.moves[k];
+        t.positive += c.positive[k];
     }
     for (int b = 0; b < MAX_BUCKETS; b++) t.qcount[b] = c.qcount[b];
     return t;
@@ -282,6 +306,9 @@ void louvain_params_default(louvain_params* p) {
     p->bucket_order = 0;
     p->async_slices = 64;
     p->async_slice_iters = 0;
+    p->guard_tolerance = 1;
+    p->pruner_weights = nullptr;
+    p->pruner_threshold = 0.5;
 }
 
 louvain_status louvain_workspace_size(const louvain_graph* g, const louvain_params* p, size_t* bytes) {
@@ -309,8 +336,14 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
         return fail(nullptr, LOUVAIN_ERR_INVALID, "offsets/indices missing");
     if (p->max_iterations < 1 || p->tol_den <= 0 || p->tol_num < 0 || p->tol_drop < 1 || p->agg_den <= 0 ||
         p->agg_num < 0 || p->pick_less < 0 || (p->mode != LOUVAIN_ASYNC && p->mode != LOUVAIN_SYNC) ||
-        (p->pruner != LOUVAIN_PRUNE_NONE && p->pruner != LOUVAIN_PRUNE_FLAGS))
+        (p->pruner != LOUVAIN_PRUNE_NONE && p->pruner != LOUVAIN_PRUNE_FLAGS &&
+         p->pruner != LOUVAIN_PRUNE_LEARNED) ||
+        (p->guard_tolerance != 0 && p->guard_tolerance != 1))
         return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid parameter value");
+    if (p->pruner == LOUVAIN_PRUNE_LEARNED && !p->pruner_weights)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "the learned pruner needs pruner_weights");
+    if (p->pruner_threshold != p->pruner_threshold)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "pruner_threshold is NaN");
     Layout lay;
     make_layout(g->n, g->nnz, &lay);
     if (!workspace || workspace_bytes < lay.total || ((uintptr_t)workspace % ALIGN) != 0)
@@ -345,9 +378,11 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
         h->err = "pinned host allocation failed";
         return bail(LOUVAIN_ERR_HIP);
     }
-    // zero control block and pruning stamps
+    // zero control block, pruning stamps and moved-iteration tags
     if (hipMemsetAsync(h->ctl(), 0, sizeof(Ctl), h->stream) != hipSuccess ||
         hipMemsetAsync(h->at<uint32_t>(lay.mark), 0, (size_t)std::max<int64_t>(g->n, 1) * 4, h->stream) !=
+            hipSuccess ||
+        hipMemsetAsync(h->at<uint32_t>(lay.f_moved), 0, (size_t)std::max<int64_t>(g->n, 1) * 4, h->stream) !=
             hipSuccess) {
         h->err = "workspace initialisation failed";
         return bail(LOUVAIN_ERR_HIP);
@@ -439,7 +474,17 @@ louvain_status Runner::run() {
     const int64_t n0 = H->g.n;
     const int64_t W = H->W;
     const int sync = P.mode == LOUVAIN_SYNC;
-    const int prune = P.pruner == LOUVAIN_PRUNE_FLAGS;
+    const int prune = P.pruner != LOUVAIN_PRUNE_NONE;
+    const int learned = P.pruner == LOUVAIN_PRUNE_LEARNED;
+    // learned pruning or sample recording needs the per-vertex feature state
+    const int learn = learned || (H->smp_buf && H->smp_rate > 0 && H->smp_cap > 0);
+    const float zt = P.pruner_threshold <= 0.0 ? -INFINITY
+                     : P.pruner_threshold >= 1.0 ? INFINITY
+                     : (float)std::log(P.pruner_threshold / (1.0 - P.pruner_threshold));
+    i64* f_own = at<i64>(Y.f_own);
+    i64* f_adv = at<i64>(Y.f_adv);
+    uint32_t* f_moved = at<uint32_t>(Y.f_moved);
+    int32_t* f_nm = at<int32_t>(Y.f_nm);
     int32_t* C = at<int32_t>(Y.C);
     int32_t* Cp = at<int32_t>(Y.Cp);
     i64* K = at<i64>(Y.K);
@@ -454,6 +499,7 @@ louvain_status Runner::run() {
     void* scan = at<void>(Y.scan);
 
     memset(&H->st, 0, sizeof(H->st));
+    H->smp_count = 0;
     H->recs.clear();
     H->evnext = 0;
     HIPCHK(H, hipMemsetAsync(ctl(), 0, sizeof(Ctl), s));
@@ -507,6 +553,7 @@ louvain_status Runner::run() {
             int64_t most = 0;
             for (auto& gr : hub_groups) most = std::max(most, hub_pre[gr.second] - hub_pre[gr.first]);
             launch_big_clear(at<int32_t>(Y.pool_keys), at<void>(Y.pool_vals), most, s);
+            HIPCHK(H, hipMemsetAsync(at<int32_t>(Y.hcnt), 0, (size_t)nhub * 4, s));
         }
         u64 kmax = 0;
         if ((st = readback(H, &kmax, &ctl()->kmax, sizeof(u64))) != LOUVAIN_OK) return st;
@@ -524,10 +571,14 @@ louvain_status Runner::run() {
         int qsel = 0;
         u64 prev_b[5][MAX_BUCKETS] = {};
         const int mode = sync ? 0 : (P.async_coherent ? 2 : 1);
+        bool sweep = learned;          // LEARNED: iteration 0 is a sweep
+        int64_t smp_lo = 0, smp_hi = 0;  // samples recorded for the current iteration
         for (int t = 0; t < P.max_iterations; t++) {
             const int pl = P.pick_less > 0 && ((t + P.pick_less / 2) % P.pick_less) == 0;
             HIPCHK(H, hipMemsetAsync(ctl(), 0, CTL_ITER_BYTES, s));
+            if (learn) HIPCHK(H, hipMemsetAsync(f_nm, 0, (size_t)n * 4, s));
             const uint32_t stamp_next = ++H->stamp;
+            if (sweep) H->st.sweeps++;
             int32_t* qnext = qbuf[qsel];
             MoveArgs a{};
             a.off = L.off;
@@ -548,11 +599,19 @@ louvain_status Runner::run() {
             a.hub_list = hub_list;
             a.hub_pre = hpre;
             a.hch_pre = hchpre;
-            a.all_queued = (t == 0 || !prune) ? 1 : 0;
+            a.all_queued = (t == 0 || !prune || sweep) ? 1 : 0;
             a.stamp_cur = stamp_next - 1;
             a.gdec = gdec;
             a.hub_keys = at<int32_t>(Y.pool_keys);
             a.hub_vals = at<void>(Y.pool_vals);
+            a.hub_cnt = at<int32_t>(Y.hcnt);
+            a.hub_slots = at<int32_t>(Y.hslots);
+            a.learn = learn;
+            a.itag = stamp_next;
+            a.f_own = f_own;
+            a.f_adv = f_adv;
+            a.f_moved = f_moved;
+            a.f_nm = f_nm;
             // hubs: chunked inserts, one decision per hub, chunked stamping, for
             // the static hub positions [s_lo, s_hi) whose tables share the pool
             const bool hubs_now = nhub > 0 && counts[NB_MOVE] > 0;
@@ -569,7 +628,8 @@ louvain_status Runner::run() {
                             launch_hub_insert(LM, mode, a, nchunks, s);
                             launch_hub_decide(LM, mode, a, s);
                         });
-                    if (mark_phase && prune) timed(H, K_HUB_MARK, 0, [&] { launch_hub_mark(L, a, nchunks, s); });
+                    if (mark_phase && (prune || learn))
+                        timed(H, K_HUB_MARK, 0, [&] { launch_hub_mark(L, a, nchunks, s); });
                 }
             };
             // ASYNC: the iteration runs as ns slices in vertex-id order (each
@@ -608,7 +668,8 @@ louvain_status Runner::run() {
                 timed(H, K_SYNC_APPLY, 0, [&] { launch_sync_apply(L, a, s); });
                 if (hubs_now) hubs_range(0, nhub, false, true);
             }
-            if (prune)
+            if (learn) launch_learn_label(H->smp_buf, smp_lo, smp_hi, f_moved, stamp_next, s);
+            if (prune && !learn)
                 timed(H, K_QUEUE, 0, [&] {
                     bucketize_vertices(n, vb, mark, stamp_next, 1, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
                 });
@@ -617,7 +678,7 @@ louvain_status Runner::run() {
             HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
             if (H->prof) HIPCHK(H, hipMemcpyAsync(&hc->bstat, &ctl()->bstat, sizeof(hc->bstat), hipMemcpyDeviceToHost, s));
             HIPCHK(H, hipStreamSynchronize(s));
-            const IterTotals it = sum_iter(*hc);
+            IterTotals it = sum_iter(*hc);
             const unsigned __int128 S = it.S;
             H->st.iterations++;
             H->st.moves += (int64_t)it.moves;
@@ -632,7 +693,8 @@ louvain_status Runner::run() {
                     const u64 de = cur[0] - prev_b[0][b];
                     if (de) {
                         const int64_t bytes = move_alg_bytes(LM, de, cur[1] - prev_b[1][b], cur[2] - prev_b[2][b],
-                                                             cur[3] - prev_b[3][b], cur[4] - prev_b[4][b], sync);
+                                                             cur[3] - prev_b[3][b], cur[4] - prev_b[4][b], sync,
+                                                             learn);
                         const int kind = b < 4 ? K_MOVE_FUSED : (b == 4 ? K_MOVE4 : K_MOVE_HUB);
                         for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
                             if (r->kind == kind) { r->bytes += bytes; break; }
@@ -648,7 +710,90 @@ louvain_status Runner::run() {
                 H->itfn(H->user, pass, t, n, hcp.data(), hsig.data(), (int64_t)it.moves, (int64_t)(S >> 64),
                         (uint64_t)S);
             }
-            if (converged(S, W, P, pass)) { li = t + 1; break; }
+            const bool conv = converged(S, W, P, pass);
+            if (!learn) {
+                if (conv) { li = t + 1; break; }
+            } else {
+                // LEARNED: only a sweep that passes the exit test ends the pass
+                if (learned ? (sweep && (P.guard_tolerance ? conv : it.positive == 0)) : conv) { li = t + 1; break; }
+                bool next_sweep = learned && !sweep && conv;
+                smp_lo = smp_hi = 0;
+                if (!next_sweep && t + 1 < P.max_iterations) {
+                    // filter (and sample) the flagged vertices of iteration t + 1
+                    const int64_t before = H->smp_count;
+                    FilterArgs fa{};
+                    fa.off = L.off;
+                    fa.n = n;
+                    fa.K = K;
+                    fa.own = f_own;
+                    fa.adv = f_adv;
+                    fa.moved = f_moved;
+                    fa.nm = f_nm;
+                    fa.itag_prev = stamp_next;
+                    fa.pass = pass;
+                    fa.t = t + 1;
+                    fa.mark = mark;
+                    fa.stamp = stamp_next;
+                    fa.all = prune ? 0 : 1;
+                    fa.learned = learned;
+                    fa.weights = P.pruner_weights;
+                    fa.zt = zt;
+                    fa.samples = H->smp_buf;
+                    fa.cap = H->smp_buf ? H->smp_cap : 0;
+                    fa.per_mille = H->smp_buf ? H->smp_rate : 0;
+                    fa.ctl = ctl();
+                    timed(H, K_LEARN_FILTER, 0, [&] { launch_learn_filter(fa, L.t.off64, s); });
+                    if (prune)
+                        timed(H, K_QUEUE, 0, [&] {
+                            bucketize_vertices(n, vb, mark, stamp_next, 1, blkcnt, blkoff, qnext, ctl()->qcount,
+                                               scan, s);
+                        });
+                    HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
+                    HIPCHK(H, hipMemcpyAsync(&hc->nsamples, &ctl()->nsamples, sizeof(u64), hipMemcpyDeviceToHost, s));
+                    HIPCHK(H, hipStreamSynchronize(s));
+                    it = sum_iter(*hc);
+                    H->smp_count = std::min<int64_t>((int64_t)hc->nsamples, H->smp_cap);
+                    smp_lo = before;
+                    smp_hi = H->smp_count;
+                    int64_t kept = 0;
+                    for (int b = 0; b < NBT; b++) kept += it.qcount[b];
+                    if (H->prof) {
+                        const int64_t flagged = prune ? kept + (int64_t)hc->pruned : nonisolated;
+                        const int64_t bytes = filter_alg_bytes(L, n, flagged, (int64_t)hc->pruned, smp_hi - smp_lo);
+                        for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
+                            if (r->kind == K_LEARN_FILTER) { r->bytes += bytes; break; }
+                    }
+                    if (learned) {
+                        if (kept == 0) next_sweep = true;  // nothing kept: certify with a sweep
+                        else H->st.pruned += (int64_t)hc->pruned;
+                    }
+                }
+                if (!next_sweep && prune && t + 1 < P.max_iterations) {
+                    int64_t total = 0;
+                    csegs[0] = 0;
+                    for (int b = 0; b < NBT; b++) {
+                        counts[b] = it.qcount[b];
+                        total += counts[b];
+                        csegs[b + 1] = csegs[b] + counts[b];
+                    }
+                    cur_list = qnext;
+                    qsel ^= 1;
+                    if (total == 0) {
+                        // flag pruning with nothing flagged: the next iteration has S = 0 and converges
+                        H->st.iterations++;
+                        if (H->itfn) H->itfn(H->user, pass, t + 1, n, hcp.data(), hsig.data(), 0, 0, 0);
+                        li = t + 2;
+                        break;
+                    }
+                }
+                if (next_sweep) {
+                    cur_list = blist;
+                    for (int b = 0; b < NBT; b++) counts[b] = bcount[b];
+                    for (int b = 0; b <= NBT; b++) csegs[b] = segs[b];
+                }
+                sweep = next_sweep;
+                continue;
+            }
             // next iteration's queue
             if (prune) {
                 int64_t total = 0;
@@ -784,7 +929,10 @@ louvain_status Runner::run() {
                 B.rowlen = A.rowlen;
                 B.bitmaps = at<uint32_t>(Y.bitmaps);
                 B.words = (ncom + 31) / 32;
+                B.cnt = at<int32_t>(Y.hcnt) + gr.first;
+                B.slots = at<int32_t>(Y.hslots);
                 const int64_t nchunks = chpre[gr.second] - chpre[gr.first];
+                HIPCHK(H, hipMemsetAsync(B.cnt, 0, (size_t)B.nbig * 4, s));
                 timed(H, K_AGG_BIG_INSERT, 0, [&] {
                     launch_big_clear(B.keys, B.vals, hub_pre[gr.second] - hub_pre[gr.first], s);
                     launch_big_insert(LA, B, nchunks, s);
@@ -981,6 +1129,114 @@ louvain_status louvain_set_trace(louvain_t* h, louvain_iter_fn iter_fn, louvain_
     h->itfn = iter_fn;
     h->pafn = pass_fn;
     h->user = user;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_collect_samples(louvain_t* h, float* buffer, int64_t capacity, int32_t sample_per_mille) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    if (buffer && (capacity < 0 || sample_per_mille < 0 || sample_per_mille > 1000))
+        return fail(h, LOUVAIN_ERR_INVALID, "capacity must be >= 0 and sample_per_mille in [0, 1000]");
+    h->smp_buf = (buffer && sample_per_mille > 0 && capacity > 0) ? buffer : nullptr;
+    h->smp_cap = h->smp_buf ? capacity : 0;
+    h->smp_rate = h->smp_buf ? sample_per_mille : 0;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_sample_count(louvain_t* h, int64_t* count) {
+    if (!h || !count) return fail(h, LOUVAIN_ERR_INVALID, "null argument");
+    *count = h->smp_count;
+    return LOUVAIN_OK;
+}
+
+// ---------------------------------------------------------- stand-alone MLP
+
+#define MLPCHK(x)                                                                               \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(nullptr, LOUVAIN_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_));  \
+    } while (0)
+
+louvain_status louvain_pruner_init(float* weights, uint64_t seed, void* stream) {
+    if (!weights) return fail(nullptr, LOUVAIN_ERR_INVALID, "null weights");
+    launch_mlp_init(weights, seed, (hipStream_t)stream);
+    MLPCHK(hipGetLastError());
+    MLPCHK(hipStreamSynchronize((hipStream_t)stream));
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_pruner_predict(const float* weights, const float* features, int64_t count, float* logit,
+                                      void* stream) {
+    if (count < 0 || (count > 0 && (!weights || !features || !logit)))
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "null argument or negative count");
+    launch_mlp_predict(weights, features, count, logit, (hipStream_t)stream);
+    MLPCHK(hipGetLastError());
+    MLPCHK(hipStreamSynchronize((hipStream_t)stream));
+    return LOUVAIN_OK;
+}
+
+int64_t louvain_pruner_scratch_floats(int32_t batch) {
+    (void)batch;  // mini-batch indices are drawn inside the kernels
+    return 3 * (int64_t)MLP_PARAMS + 5;  // gradient, two Adam moments, an 8-byte-aligned double
+}
+
+namespace {
+// The double accumulator sits after 3 * MLP_PARAMS floats, rounded up to 8 bytes.
+double* scratch_loss(float* scratch) {
+    uintptr_t p = (uintptr_t)(scratch + 3 * MLP_PARAMS);
+    return (double*)((p + 7) & ~(uintptr_t)7);
+}
+}  // namespace
+
+louvain_status louvain_pruner_loss_grad(const float* weights, const float* samples, int64_t count,
+                                        float pos_weight, float* grad, double* loss, void* stream) {
+    if (!weights || !grad || count < 0 || (count > 0 && !samples))
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "null argument or negative count");
+    hipStream_t s = (hipStream_t)stream;
+    double* acc = nullptr;
+    MLPCHK(hipMalloc(&acc, sizeof(double)));
+    launch_mlp_zero(grad, MLP_PARAMS, s);
+    hipError_t e = hipMemsetAsync(acc, 0, sizeof(double), s);
+    if (e == hipSuccess) {
+        launch_mlp_loss_grad(weights, samples, count, count, 0, 0, 0, pos_weight, grad, acc, s);
+        e = hipGetLastError();
+    }
+    double hv = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hv, acc, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(acc);
+    if (e != hipSuccess) return fail(nullptr, LOUVAIN_ERR_HIP, "pruner loss: %s", hipGetErrorString(e));
+    if (loss) *loss = hv;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_pruner_train(float* weights, const float* samples, int64_t count, int32_t steps,
+                                    int32_t batch, float lr, float pos_weight, uint64_t seed, float* scratch,
+                                    double* last_loss, void* stream) {
+    if (!weights || !scratch || count <= 0 || !samples || steps < 0 || batch <= 0)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid arguments (need samples, count > 0, batch > 0)");
+    hipStream_t s = (hipStream_t)stream;
+    float* grad = scratch;
+    float* m = scratch + MLP_PARAMS;
+    float* v = scratch + 2 * MLP_PARAMS;
+    double* acc = scratch_loss(scratch);
+    launch_mlp_zero(m, 2 * MLP_PARAMS, s);
+    const bool full = batch >= count;
+    const int64_t slots = full ? count : batch;
+    double b1t = 1.0, b2t = 1.0;
+    for (int32_t step = 0; step < steps; step++) {
+        launch_mlp_zero(grad, MLP_PARAMS, s);
+        launch_mlp_zero((float*)acc, 2, s);
+        launch_mlp_loss_grad(weights, samples, count, slots, full ? 0 : batch, seed, step, pos_weight, grad, acc, s);
+        b1t *= 0.9;
+        b2t *= 0.999;
+        launch_adam(weights, grad, m, v, lr, (float)(1.0 - b1t), (float)(1.0 - b2t), s);
+    }
+    MLPCHK(hipGetLastError());
+    double hv = 0;
+    if (steps > 0) MLPCHK(hipMemcpyAsync(&hv, acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    MLPCHK(hipStreamSynchronize(s));
+    if (last_loss) *last_loss = hv;
     return LOUVAIN_OK;
 }
 

@@ -5,7 +5,8 @@
 // K, community totals Sigma and super-graph weights are int64; modularity
 // gains (Eq. (2) of the paper, multiplied by W^2/2) are int64 when
 // W * max(K) < 2^62 and __int128 otherwise; per-iteration gain sums are
-// 128-bit.  Nothing in the hot path uses floating point.
+// 128-bit.  Floating point appears only in the optional learned pruner
+// (lv_learn.hip), whose FP32 keep decisions follow a fixed operation order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,6 +36,8 @@ struct Ctl {
     u64 s_lo[STRIPES];            // 128-bit sums of applied gains (two's complement)
     u64 s_hi[STRIPES];
     u64 moves[STRIPES];           // moves applied
+    u64 positive[STRIPES];        // evaluated vertices whose best gain was positive (before Pick-Less)
+    u64 pruned;                   // flagged vertices the learned pruner skipped (for the next iteration)
     // ---- other state
     int32_t err;                  // validation error bits
     int32_t nonisolated;
@@ -44,6 +47,7 @@ struct Ctl {
     int32_t bcursor[MAX_BUCKETS]; // fill cursors
     u64 q_lo;                     // modularity numerator accumulator (128-bit)
     u64 q_hi;
+    u64 nsamples;                 // training samples claimed during the run
     // ---- run totals per move bucket (last = hub): evaluations, arcs,
     // distinct communities, moves, arcs of movers
     u64 bstat[5][MAX_BUCKETS][STRIPES];
@@ -85,6 +89,25 @@ __device__ __forceinline__ void table_add(int32_t* keys, AccT* vals, uint32_t ma
         if (k == EMPTY_KEY) {
             int32_t old = atomicCAS(&keys[s], EMPTY_KEY, key);
             if (old == EMPTY_KEY || old == key) { atomicAdd(&vals[s], v); return; }
+        }
+        s = (s + step) & mask;
+    }
+}
+
+// As table_add; returns the slot if this call claimed a previously empty
+// slot for key, else -1 (so that callers can list the occupied slots).
+template <typename AccT>
+__device__ __forceinline__ int64_t table_add_claim(int32_t* keys, AccT* vals, uint32_t mask, uint32_t s,
+                                                   int32_t key, AccT v) {
+    for (uint32_t step = 1;; ++step) {
+        int32_t k = *(volatile int32_t*)&keys[s];
+        if (k == key) { atomicAdd(&vals[s], v); return -1; }
+        if (k == EMPTY_KEY) {
+            int32_t old = atomicCAS(&keys[s], EMPTY_KEY, key);
+            if (old == EMPTY_KEY || old == key) {
+                atomicAdd(&vals[s], v);
+                return old == EMPTY_KEY ? (int64_t)s : -1;
+            }
         }
         s = (s + step) & mask;
     }

@@ -68,6 +68,40 @@ struct MoveArgs {
     int32_t* gdec;           // per static hub: applied (ASYNC) or recorded (SYNC) target, or -1
     int32_t* hub_keys;
     void* hub_vals;
+    int32_t* hub_cnt;        // per static hub: occupied slots of its table (0 between iterations)
+    int32_t* hub_slots;      // occupied slot lists: hub h's list starts at its table offset / 2
+    // per-vertex state of the learned pruner's features (learn = 1)
+    int32_t learn;
+    uint32_t itag;           // tag of this iteration, unique within the run
+    i64* f_own;              // K_{v->C'[v]} at v's last evaluation
+    i64* f_adv;              // K_{v->d*} - K_{v->C'[v]} at v's last evaluation
+    uint32_t* f_moved;       // tag of the last iteration in which v moved
+    int32_t* f_nm;           // moved neighbours of v in this iteration (cleared before it)
+};
+
+// Learned-pruner filter of the next iteration's queue (lv_learn.hip).
+constexpr int MLP_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1;
+constexpr int SAMPLE_FLOATS = 9;
+struct FilterArgs {
+    const void* off;
+    int64_t n;
+    const i64* K;
+    const i64* own;
+    const i64* adv;
+    const uint32_t* moved;
+    const int32_t* nm;
+    uint32_t itag_prev;   // tag of the iteration that just ended
+    int32_t pass, t;      // of the iteration the queue is for
+    uint32_t* mark;
+    uint32_t stamp;       // flagged iff mark == stamp ...
+    int32_t all;          // ... or, with all = 1, every vertex with an arc
+    int32_t learned;      // apply the MLP
+    const float* weights;
+    float zt;             // keep iff logit >= zt
+    float* samples;
+    int64_t cap;
+    int32_t per_mille;
+    Ctl* ctl;
 };
 
 // Lists of buckets 0..3 for one fused launch; blk_pre[b] is the first block
@@ -113,6 +147,15 @@ void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, hipStrea
 void launch_hub_mark(const LevelView& L, const MoveArgs& a, int64_t nchunks, hipStream_t s);
 void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const FusedLists& f, hipStream_t s);
 void launch_sync_apply(const LevelView& L, const MoveArgs& a, hipStream_t s);
+void launch_learn_filter(const FilterArgs& f, int off64, hipStream_t s);
+void launch_learn_label(float* samples, int64_t lo, int64_t hi, const uint32_t* moved, uint32_t itag,
+                        hipStream_t s);
+void launch_mlp_init(float* w, u64 seed, hipStream_t s);
+void launch_mlp_predict(const float* w, const float* X, int64_t count, float* out, hipStream_t s);
+void launch_mlp_zero(float* p, int64_t n, hipStream_t s);
+void launch_mlp_loss_grad(const float* w, const float* S, int64_t count, int64_t slots, int32_t batch, u64 seed,
+                          int64_t step, float pos_weight, float* grad, double* loss, hipStream_t s);
+void launch_adam(float* w, const float* g, float* m, float* v, float lr, float bc1, float bc2, hipStream_t s);
 
 // ---- launchers: aggregation and modularity (lv_aggr.hip)
 struct AggArgs {
@@ -165,7 +208,10 @@ struct BigArgs {
     int32_t* rowlen;
     uint32_t* bitmaps;         // BIG_EXTRACT_BLOCKS * words
     int64_t words;             // ceil(ncom / 32)
+    int32_t* cnt;              // per big community of the group: occupied table slots (zeroed by the host)
+    int32_t* slots;            // occupied slot lists, community h's at its table offset / 2
 };
+constexpr int BIG_SORT_MAX = 8192;  // rows up to this length are sorted in LDS at extraction
 void launch_member_deg(const LevelView& L, const int32_t* members, int64_t n, int64_t* md, hipStream_t s);
 void launch_big_info(const int32_t* list, int32_t nbig, const int64_t* hoff, int64_t ncom, int64_t* nch,
                      int64_t* cap, hipStream_t s);

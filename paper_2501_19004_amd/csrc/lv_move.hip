@@ -241,18 +241,24 @@ struct Decision {
     i64 kic;         // K_{i->c}
     i128 gain;       // gain against the state read
     i64 nd;          // distinct neighbour communities
+    i64 bestk;       // K_{i->d*} of the best candidate d* (0 without one)
+    int32_t positive;  // the best candidate's gain was positive (before Pick-Less)
 };
 
 // Per-group decision after the table is filled.  Scans the table slots owned
-// by this lane, reduces over the group; every lane returns the same result.
+// by this lane (all cap slots, or the nlist slots listed in `list`), reduces
+// over the group; every lane returns the same result.
 template <int G, int MODE, typename KeyT, typename AccT>
 __device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* keys, const AccT* vals, int64_t cap,
                                            int lane, bool active, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
-                                           i64* s_v, i64* s_t) {
+                                           i64* s_v, i64* s_t, const int32_t* list = nullptr,
+                                           int64_t nlist = 0) {
     KeyT bk = 0;
     int32_t bd = EMPTY_KEY;
     i64 bv = 0, kic = 0, nd = 0;
-    for (int64_t s = lane; s < cap; s += G) {
+    const int64_t span = list ? nlist : cap;
+    for (int64_t k = lane; k < span; k += G) {
+        const int64_t s = list ? (int64_t)list[k] : k;
         const int32_t d = keys[s];
         if (d == EMPTY_KEY) continue;
         ++nd;
@@ -265,11 +271,12 @@ __device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* key
     if (bd == EMPTY_KEY) bk = (sizeof(KeyT) == 8) ? (KeyT)INT64_MIN : (KeyT)(((i128)1) << 127);
     reduce_best<G, KeyT>(bk, bd, bv, s_k, s_d, s_v);
     kic = reduce_max<G>(kic, s_t);
-    Decision r{-1, 0, kic, 0, reduce_sum<G>(nd, s_t)};
+    Decision r{-1, 0, kic, 0, reduce_sum<G>(nd, s_t), bd != EMPTY_KEY ? bv : 0, 0};
     if (active && bd != EMPTY_KEY) {
         const i64 Sc = ld_s<MODE>(&a.Sig[c]);
         const KeyT stay = (KeyT)a.W * kic - (KeyT)Ki * (Sc - Ki);
         const KeyT gk = bk - stay;
+        r.positive = gk > 0;
         if (gk > 0 && (!a.pl || bd < c)) { r.target = bd; r.kid = bv; r.gain = (i128)gk; }
     }
     return r;
@@ -288,6 +295,7 @@ __device__ __forceinline__ bool apply_async(const MoveArgs& a, int32_t i, int32_
     if (g > 0) {
         atomicAdd((u64*)&a.Sig[c], (u64)(-Ki));
         st_c<MODE>(&a.Cp[i], dcs.target);
+        if (a.learn) a.f_moved[i] = a.itag;
         dcs.gain = g;
         return true;
     }
@@ -297,20 +305,31 @@ __device__ __forceinline__ bool apply_async(const MoveArgs& a, int32_t i, int32_
     return false;
 }
 
-// Stamp the neighbours of mover i for the next iteration's queue.
+// Stamp the neighbours of mover i for the next iteration's queue (pruning)
+// and count i among their moved neighbours (learned-pruner features).
+__device__ __forceinline__ void mark_one(const MoveArgs& a, int32_t i, int32_t j) {
+    if (j == i) return;
+    if (a.prune && a.mark[j] != a.stamp_next) a.mark[j] = a.stamp_next;
+    if (a.learn) atomicAdd(&a.f_nm[j], 1);
+}
 template <int G, typename OffT, int WK>
 __device__ __forceinline__ void mark_neighbours(const MoveArgs& a, const Graph<OffT, WK>& g, int32_t i, i64 o0,
                                                 i64 o1, int lane) {
-    for (i64 e = o0 + lane; e < o1; e += G) {
-        const int32_t j = g.idx[e];
-        if (j != i && a.mark[j] != a.stamp_next) a.mark[j] = a.stamp_next;
-    }
+    for (i64 e = o0 + lane; e < o1; e += G) mark_one(a, i, g.idx[e]);
+}
+
+// Feature state of an evaluated vertex: its own-community weight and the
+// best candidate's advantage over it.
+__device__ __forceinline__ void note_evaluation(const MoveArgs& a, int32_t i, const Decision& d) {
+    a.f_own[i] = d.kic;
+    a.f_adv[i] = d.bestk - d.kic;
 }
 
 __device__ __forceinline__ void add_block_totals(Ctl* ctl, int bucket, u64 ne, u64 na, u64 nd, u64 nm, u64 nma,
-                                                 i128 gain) {
+                                                 i128 gain, u64 npos) {
     const int st = blockIdx.x & (STRIPES - 1);
     if (!ne) return;
+    if (npos) atomicAdd(&ctl->positive[st], npos);
     atomicAdd(&ctl->bstat[0][bucket][st], ne);
     atomicAdd(&ctl->bstat[1][bucket][st], na);
     atomicAdd(&ctl->bstat[2][bucket][st], nd);
@@ -333,6 +352,7 @@ struct MoveShm {
     int32_t x[1];
     i128 gain[32];
     int32_t dec[32];
+    int32_t pos[32];
     i64 arcs[32], nd[32];
 };
 
@@ -374,32 +394,35 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
         ? decide<G, MODE, i64, AccT>(a, keys, vals, CAP, lane, active, c, Ki, sh.k64, sh.d, sh.v, sh.t)
         : decide<G, MODE, i128, AccT>(a, keys, vals, CAP, lane, active, c, Ki, sh.k128, sh.d, sh.v, sh.t);
 
+    if (a.learn && active && lane == 0) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
         wave_append_pair(lane == 0 && dcs.target >= 0, i, dcs.target, a.movers, &a.ctl->movers);
     } else {
         int32_t t = -1;
         if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, i, c, Ki, dcs)) t = dcs.target;
         t = group_bcast<G>(t, sh.x);
-        if (a.prune && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
+        if ((a.prune || a.learn) && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
     }
     if (lane == 0) {
         sh.gain[grp] = dcs.gain;
         sh.dec[grp] = dcs.target;
+        sh.pos[grp] = active ? dcs.positive : 0;
         sh.arcs[grp] = active ? (o1 - o0) : -1;
         sh.nd[grp] = dcs.nd;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         i128 sg = 0;
-        u64 nm = 0, ne = 0, na = 0, ndt = 0, nma = 0;
+        u64 nm = 0, ne = 0, na = 0, ndt = 0, nma = 0, np = 0;
         for (int k = 0; k < NG; k++) {
             if (sh.arcs[k] < 0) continue;
             ne++;
             na += (u64)sh.arcs[k];
             ndt += (u64)sh.nd[k];
+            np += (u64)sh.pos[k];
             if (sh.dec[k] >= 0) { sg += sh.gain[k]; nm++; nma += (u64)sh.arcs[k]; }
         }
-        add_block_totals(a.ctl, bucket, ne, na, ndt, nm, nma, sg);
+        add_block_totals(a.ctl, bucket, ne, na, ndt, nm, nma, sg, np);
     }
 }
 
@@ -503,9 +526,13 @@ __global__ void __launch_bounds__(1024) k_hub_insert(MoveArgs a) {
     const int log2cap = __ffsll((long long)cap) - 1;
     int32_t* keys = a.hub_keys + toff;
     AccT* vals = (AccT*)a.hub_vals + toff;
+    int32_t* slots = a.hub_slots + toff / 2;  // cap >= 2 * distinct keys, so cap / 2 list entries suffice
     for (int s = tid; s < HUB_LCAP; s += G) {
         const int32_t d = s_keys[s];
-        if (d != EMPTY_KEY) table_add<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d, s_vals[s]);
+        if (d == EMPTY_KEY) continue;
+        const int64_t got = table_add_claim<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d,
+                                                  s_vals[s]);
+        if (got >= 0) slots[atomicAdd(&a.hub_cnt[h], 1)] = (int32_t)got;
     }
 }
 
@@ -529,12 +556,20 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
     const int64_t cap = a.hub_pre[h + 1] - a.hub_pre[h];
     int32_t* keys = a.hub_keys + toff;
     AccT* vals = (AccT*)a.hub_vals + toff;
+    const int32_t* slots = a.hub_slots + toff / 2;
+    const int64_t nocc = a.hub_cnt[h];
     const int32_t c = ld_c<MODE>(&a.Cp[v]);
     const i64 Ki = a.K[v];
     Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k64, s_d, s_v, s_t)
-        : decide<G, MODE, i128, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k128, s_d, s_v, s_t);
-    for (int64_t s = tid; s < cap; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }  // clean for the next iteration
+        ? decide<G, MODE, i64, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k64, s_d, s_v, s_t, slots, nocc)
+        : decide<G, MODE, i128, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k128, s_d, s_v, s_t, slots, nocc);
+    // clean the occupied slots for the next iteration
+    for (int64_t k = tid; k < nocc; k += G) {
+        const int32_t sl = slots[k];
+        keys[sl] = EMPTY_KEY;
+        vals[sl] = 0;
+    }
+    if (tid == 0) a.hub_cnt[h] = 0;
     const i64 deg = (i64)off[v + 1] - (i64)off[v];
     if (tid == 0) {
         if constexpr (MODE == M_SYNC) {
@@ -546,9 +581,10 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
         } else {
             if (dcs.target >= 0) apply_async<MODE>(a, v, c, Ki, dcs);
         }
+        if (a.learn) note_evaluation(a, v, dcs);
         a.gdec[h] = dcs.target;
         add_block_totals(a.ctl, a.bucket, 1, (u64)deg, (u64)dcs.nd, dcs.target >= 0 ? 1 : 0,
-                         dcs.target >= 0 ? (u64)deg : 0, dcs.gain);
+                         dcs.target >= 0 ? (u64)deg : 0, dcs.gain, (u64)dcs.positive);
     }
 }
 
@@ -563,10 +599,7 @@ __global__ void __launch_bounds__(1024) k_hub_mark(MoveArgs a) {
     const int64_t k = (int64_t)blockIdx.x - (a.hch_pre[h] - chunk_base);
     const i64 e0 = (i64)off[v] + k * HUB_CH;
     const i64 e1 = min(e0 + (i64)HUB_CH, (i64)off[v + 1]);
-    for (i64 e = e0 + threadIdx.x; e < e1; e += 1024) {
-        const int32_t j = a.idx[e];
-        if (j != v && a.mark[j] != a.stamp_next) a.mark[j] = a.stamp_next;
-    }
+    for (i64 e = e0 + threadIdx.x; e < e1; e += 1024) mark_one(a, v, a.idx[e]);
 }
 
 // SYNC: apply the recorded decisions together, then stamp the movers'
@@ -585,8 +618,10 @@ __global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a) {
             atomicAdd((u64*)&a.Sig[c], (u64)(-Ki));
             atomicAdd((u64*)&a.Sig[d], (u64)Ki);
             a.Cp[i] = d;
+            if (a.learn) a.f_moved[i] = a.itag;
         }
-        if (a.prune && a.vbucket[i] != NB_MOVE) mark_neighbours<WAVE>(a, g, i, (i64)g.off[i], (i64)g.off[i + 1], lane);
+        if ((a.prune || a.learn) && a.vbucket[i] != NB_MOVE)
+            mark_neighbours<WAVE>(a, g, i, (i64)g.off[i], (i64)g.off[i + 1], lane);
     }
 }
 

@@ -39,11 +39,53 @@ def test_params_default_are_the_papers(lib):
     assert (p.agg_num, p.agg_den, p.pick_less, p.mode, p.pruner) == (4, 5, 4, lv.ASYNC, lv.PRUNE_FLAGS)
 
 
-def test_struct_sizes_match_header(lib):
-    # louvain_graph: 2 int64 + int32 (+pad) + 3 pointers
-    assert ctypes.sizeof(lv.LouvainGraph) == 48
-    assert ctypes.sizeof(lv.LouvainParams) == 4 * 2 + 8 * 5 + 4 * 4 + 4 * 24
-    assert ctypes.sizeof(lv.LouvainKernelStat) == 48 + 8 * 3
+STRUCTS = {"louvain_graph": "LouvainGraph", "louvain_params": "LouvainParams", "louvain_stats": "LouvainStats",
+           "louvain_kernel_stat": "LouvainKernelStat"}
+
+
+def test_struct_layouts_match_header(lib, tmp_path):
+    """Every ctypes field sits at the offset the C compiler gives it in
+    include/louvain.h, and every struct has the header's size."""
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "louvain.h"', "int main(void) {"]
+    for cname, pname in STRUCTS.items():
+        cls = getattr(lv, pname)
+        lines.append(f'printf("{pname} size %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{pname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, pname in STRUCTS.items():
+        cls = getattr(lv, pname)
+        assert got[(pname, "size")] == ctypes.sizeof(cls), pname
+        for f in cls._fields_:
+            assert got[(pname, f[0])] == getattr(cls, f[0]).offset, (pname, f[0])
+
+
+def test_learned_entry_points_reject_bad_arguments(lib):
+    assert lib.louvain_collect_samples(None, None, 0, 0) == lv.LOUVAIN_ERR_INVALID
+    assert lib.louvain_sample_count(None, None) == lv.LOUVAIN_ERR_INVALID
+    assert lib.louvain_pruner_init(None, 1, None) == lv.LOUVAIN_ERR_INVALID
+    assert lib.louvain_pruner_predict(None, None, -1, None, None) == lv.LOUVAIN_ERR_INVALID
+    assert lib.louvain_pruner_loss_grad(None, None, 5, 1.0, None, None, None) == lv.LOUVAIN_ERR_INVALID
+    assert lib.louvain_pruner_train(None, None, 0, 1, 1, 1e-3, 1.0, 0, None, None, None) == lv.LOUVAIN_ERR_INVALID
+    assert lib.louvain_pruner_scratch_floats(4096) >= 3 * lv.MLP_PARAMS + 2
+    fake = 4096
+    g = lv.LouvainGraph(10, 20, 32, fake, fake, None)
+    p = lv.louvain_params_default()
+    p.pruner = lv.PRUNE_LEARNED
+    assert _create_status(g, p)[0] == lv.LOUVAIN_ERR_INVALID            # learned pruner without weights
+    assert "pruner_weights" in lv.louvain_last_error(None)
+    p = lv.louvain_params_default()
+    p.guard_tolerance = 2
+    assert _create_status(g, p)[0] == lv.LOUVAIN_ERR_INVALID
+    p = lv.louvain_params_default()
+    assert (p.guard_tolerance, p.pruner_weights, p.pruner_threshold) == (1, None, 0.5)
 
 
 def test_workspace_size_is_host_only_and_monotone(lib):

@@ -1,0 +1,248 @@
+"""GPU parity of the learned move-pruner, through the C ABI.
+
+SYNC runs with the learned pruner must match the oracle bit for bit: every
+iteration's C' and Sigma', the super-graphs, the final membership, and the
+numbers of sweeps and pruned vertices (the FP32 features and MLP follow the
+same fixed operation order on both sides, so every keep decision agrees).
+Recorded training samples must equal the oracle's as multisets of rows.  The
+stand-alone MLP kernels are checked against the oracle's FP32 logits (exact)
+and its float64 loss, gradient and Adam step (tolerance).  ASYNC runs must
+reach modularity within 0.002 of the oracle's sequential run with the same
+pruner, and the strict guard must leave no positive-gain move.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import oracle.mlp as mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lv = pytest.importorskip("paper_2501_19004_amd")
+
+ALL_HUB = dict(bucket_max_degree=[-1] * 5, agg_bucket_max=[-1] * 4)
+SMALL_B = dict(bucket_max_degree=[2, 8, 16, 64, 128], agg_bucket_max=[4, 16, 64, 256])
+CONFIGS = {"default": {}, "all_hub": ALL_HUB, "small_buckets": SMALL_B}
+GRAPHS = {
+    "planted": lambda: gg.planted_partition(seed=6),
+    "rmat12w": lambda: gg.rmat(12, 16, seed=4, wmax=7),
+    "sbm": lambda: gg.sbm_degree(6000, 24, 14.0, seed=6, wmin=1, wmax=4),
+    "loops": lambda: gg.random_small(60, 0.12, 3, wmax=5, self_loops=True),
+}
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+def rand_weights(seed, scale=0.4):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(mlp.N_PARAMS) * scale).astype(np.float32)
+
+
+def run_gpu(g, mode, wts=None, sample_rate=0, trace=True, **kw):
+    off, idx, w = lv.graph_tensors(g, dev())
+    if wts is not None:
+        kw = dict(kw, pruner=lv.PRUNE_LEARNED, pruner_weights=torch.from_numpy(wts).to(dev()))
+    L = lv.Louvain(off, idx, w, mode=mode, **kw)
+    buf = L.collect_samples(200000, sample_rate) if sample_rate else None
+    iters, graphs = [], []
+    if trace:
+        L.trace(lambda p, t, cp, sig, m, gain: iters.append((p, t, cp, sig, m, gain)),
+                lambda p, n, o, i, ww, it: graphs.append((n, o, i, ww)))
+    L.run()
+    memb = L.membership().cpu().numpy()
+    q = L.modularity()
+    st = L.stats()
+    smp = buf[:L.sample_count()].cpu().numpy() if sample_rate else None
+    L.close()
+    return memb, q, iters, graphs, st, smp
+
+
+def oracle_params(mode, wts=None, **kw):
+    p = oracle.Params(mode=mode)
+    if wts is not None:
+        p.prune, p.mlp = oracle.PRUNE_LEARNED, wts
+    for k, v in kw.items():
+        if k == "pruner":
+            p.prune = v
+        elif k == "pruner_threshold":
+            p.threshold = v
+        elif hasattr(p, k):
+            setattr(p, k, v)
+    return p
+
+
+def sorted_rows(a):
+    a = np.asarray(a, dtype=np.float32).reshape(-1, 9)
+    return a[np.lexsort(a.T[::-1])]
+
+
+def assert_sync_equal(g, wts, kw, sample_rate=0):
+    memb, (q, num, den), iters, graphs, st, smp = run_gpu(g, lv.SYNC, wts, sample_rate, **kw)
+    P = oracle_params(oracle.SYNC, wts, sample_per_mille=sample_rate,
+                      **{k: v for k, v in kw.items() if k not in ("bucket_max_degree", "agg_bucket_max")})
+    ref = oracle.louvain(g, P, trace=True, samples=bool(sample_rate))
+    assert len(iters) == len(ref.iters)
+    for a, b in zip(iters, ref.iters):
+        where = f"pass {b['pass_']} iter {b['iter']}"
+        assert (a[0], a[1]) == (b["pass_"], b["iter"]), where
+        assert np.array_equal(a[2], b["cprime"]), where
+        assert np.array_equal(a[3], b["sigma"]), where
+        assert (a[4], a[5]) == (b["moves"], b["gain"]), where
+    assert len(graphs) == len(ref.graphs)
+    for a, b in zip(graphs, ref.graphs):
+        assert a[0] == b["n"] and np.array_equal(a[1], b["offsets"]) and np.array_equal(a[2], b["indices"])
+        assert np.array_equal(a[3], b["weights"])
+    assert np.array_equal(memb, ref.membership)
+    assert (num, den) == oracle.modularity_parts(g, memb)
+    if wts is not None:
+        assert (st.sweeps, st.pruned) == (ref.sweeps, ref.pruned)
+    if sample_rate:
+        exp = [np.concatenate([f, [lab]]) for _, _, _, f, lab in ref.samples]
+        assert len(smp) == len(exp) and len(exp) > 0
+        assert np.array_equal(sorted_rows(smp), sorted_rows(exp))
+    return st, ref
+
+
+@pytest.mark.parametrize("theta,guard", [(0.5, 1), (0.65, 0), (1.0, 1), (0.0, 0)])
+@pytest.mark.parametrize("cfg", list(CONFIGS))
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_sync_learned_bit_exact(name, cfg, theta, guard):
+    st, ref = assert_sync_equal(GRAPHS[name](), rand_weights(3), dict(CONFIGS[cfg], pruner_threshold=theta,
+                                                                    guard_tolerance=guard))
+    assert st.sweeps >= st.passes
+
+
+@pytest.mark.parametrize("name", ["planted", "rmat12w", "sbm"])
+def test_sync_samples_flag_pruning(name):
+    """Recording samples under flag pruning changes nothing and yields the
+    oracle's samples."""
+    assert_sync_equal(GRAPHS[name](), None, {}, sample_rate=1000)
+
+
+@pytest.mark.parametrize("name", ["planted", "rmat12w"])
+def test_sync_samples_learned_and_unpruned(name):
+    assert_sync_equal(GRAPHS[name](), rand_weights(3), dict(pruner_threshold=0.5), sample_rate=300)
+    assert_sync_equal(GRAPHS[name](), None, dict(pruner=lv.PRUNE_NONE), sample_rate=150)
+
+
+def test_sample_capacity_truncates():
+    g = GRAPHS["rmat12w"]()
+    off, idx, w = lv.graph_tensors(g, dev())
+    L = lv.Louvain(off, idx, w, mode=lv.SYNC)
+    buf = L.collect_samples(50, 1000)
+    L.run()
+    assert L.sample_count() == 50
+    rows = buf[:50].cpu().numpy()
+    assert set(np.unique(rows[:, 8])) <= {0.0, 1.0}
+    L.close()
+
+
+@pytest.mark.parametrize("make", [lambda: gg.planted_partition(seed=2), lambda: gg.rmat(14, 16, seed=5),
+                                  lambda: gg.sbm_degree(20000, 32, 16.0, seed=7, wmin=1, wmax=4)],
+                         ids=["planted", "rmat14", "sbm20k"])
+@pytest.mark.parametrize("theta", [0.45, 0.55])
+def test_async_learned_quality(make, theta):
+    g = make()
+    wts = rand_weights(3)
+    memb, (q, num, den), _, _, st, _ = run_gpu(g, lv.ASYNC, wts, trace=False, pruner_threshold=theta)
+    ref = oracle.louvain(g, oracle_params(oracle.ASYNC, wts, pruner_threshold=theta))
+    qo = oracle.modularity(g, ref.membership)
+    assert (num, den) == oracle.modularity_parts(g, memb)
+    print(f"Q_gpu - Q_oracle = {q - qo:+.5f} (sweeps {st.sweeps}, pruned {st.pruned})")
+    assert q >= qo - 0.002, (q, qo)
+
+
+def _best_gain(off, idx, w, C, S, K, W, v):
+    acc = {}
+    for e in range(off[v], off[v + 1]):
+        j = int(idx[e])
+        if j != v:
+            acc[int(C[j])] = acc.get(int(C[j]), 0) + int(w[e])
+    c = int(C[v])
+    kic = acc.get(c, 0)
+    gains = [W * (kd - kic) - int(K[v]) * (int(S[d]) - int(S[c]) + int(K[v])) for d, kd in acc.items() if d != c]
+    return max(gains) if gains else None
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5, 1.0])
+def test_async_strict_guard_leaves_no_positive_move(theta):
+    g = gg.planted_partition(seed=8)
+    memb, _, iters, _, st, _ = run_gpu(g, lv.ASYNC, rand_weights(3), pruner_threshold=theta, guard_tolerance=0,
+                                       max_passes=1, max_iterations=60)
+    assert st.iterations < 60
+    C = iters[-1][2]
+    off, idx, w = g.offsets, g.indices, g.weights.astype(np.int64)
+    K = [int(w[off[v]:off[v + 1]].sum()) for v in range(g.n)]
+    W = sum(K)
+    S = np.zeros(g.n, dtype=object)
+    for v in range(g.n):
+        S[C[v]] += K[v]
+    for v in range(g.n):
+        gb = _best_gain(off, idx, w, C, S, K, W, v)
+        assert gb is None or gb <= 0, v
+
+
+# ------------------------------------------------------ stand-alone MLP
+
+def test_mlp_init_matches_oracle():
+    for seed in (0, 7, 2 ** 40 + 3):
+        w = lv.pruner_init(seed, dev()).cpu().numpy()
+        assert np.array_equal(w, mlp.glorot_init(seed))
+
+
+def test_mlp_predict_bit_exact():
+    rng = np.random.default_rng(5)
+    for s in range(3):
+        wts = rand_weights(10 + s)
+        X = (rng.random((1000, 8)) * 2 - 0.5).astype(np.float32)
+        X[:, 4] = (X[:, 4] > 0.5)
+        got = lv.pruner_predict(torch.from_numpy(wts).to(dev()), torch.from_numpy(X).to(dev())).cpu().numpy()
+        assert np.array_equal(got, oracle.mlp_logit(wts, X))
+
+
+def _samples(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, 8)).astype(np.float32)
+    y = ((X[:, 3] + 0.3 * X[:, 7] + 0.2 * rng.standard_normal(n)) > 0.6).astype(np.float32)
+    return np.concatenate([X, y[:, None]], axis=1).astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 255, 3000])
+def test_mlp_loss_grad_matches_float64(n):
+    S = _samples(n, n)
+    wts = rand_weights(4)
+    loss, grad = lv.pruner_loss_grad(torch.from_numpy(wts).to(dev()), torch.from_numpy(S).to(dev()), 2.5)
+    L64, g64 = mlp.loss_grad(wts.astype(np.float64), S[:, :8], S[:, 8], 2.5)
+    assert loss == pytest.approx(L64, rel=1e-4)
+    g = grad.cpu().numpy().astype(np.float64)
+    assert np.allclose(g, g64, rtol=2e-3, atol=1e-5 * max(1.0, np.abs(g64).max()))
+
+
+def test_mlp_train_one_full_batch_step_is_adam():
+    S = _samples(500, 1)
+    wts = rand_weights(6)
+    w = torch.from_numpy(wts.copy()).to(dev())
+    loss = lv.pruner_train(w, torch.from_numpy(S).to(dev()), steps=1, batch=4096, lr=0.01, pos_weight=2.0)
+    L64, g64 = mlp.loss_grad(wts.astype(np.float64), S[:, :8], S[:, 8], 2.0)
+    w64, _, _ = mlp.adam_step(wts.astype(np.float64), g64, np.zeros_like(g64), np.zeros_like(g64), 1, 0.01)
+    assert loss == pytest.approx(L64, rel=1e-4)
+    moved = np.abs(g64) > 1e-4  # parameters whose Adam step is a clear +-lr
+    assert np.allclose(w.cpu().numpy()[moved], w64[moved], atol=2e-4)
+
+
+def test_mlp_training_reduces_loss():
+    S = _samples(20000, 2)
+    w = lv.pruner_init(3, dev())
+    St = torch.from_numpy(S).to(dev())
+    before, _ = lv.pruner_loss_grad(w, St, 1.0)
+    last = lv.pruner_train(w, St, steps=300, batch=1024, lr=3e-3, pos_weight=1.0, seed=9)
+    after, _ = lv.pruner_loss_grad(w, St, 1.0)
+    assert after < 0.75 * before and last < before
