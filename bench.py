@@ -109,8 +109,9 @@ def learned_leg(lv, torch, g, off, idx, w, mode, args, q_plain, dt_plain):
     t_train = time.time() - t0
     print(f"[bench] pruner: {S.shape[0]} samples ({pos:.3f} moved), loss {loss0:.4f} -> {loss:.4f}, "
           f"{t_train:.1f}s", file=sys.stderr, flush=True)
+    extra = {} if args.async_coherent is None else {"async_coherent": args.async_coherent}
     L = lv.Louvain(off, idx, w, mode=mode, pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
-                   pruner_threshold=args.threshold, async_coherent=args.async_coherent)
+                   pruner_threshold=args.threshold, **extra)
     dt, q, st = timed_runs(L, args.steps, args.warmup)
     L.close()
     print(f"[bench] learned: {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), sweeps={st.sweeps} "
@@ -140,8 +141,8 @@ def main():
     ap.add_argument("--threshold", type=float, default=0.5, help="learned pruner: keep iff sigmoid >= threshold")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration run) and exit")
-    ap.add_argument("--async-coherent", type=int, default=1, choices=[0, 1],
-                    help="ASYNC: device-coherent loads of C' and Sigma' (1) or cached loads (0)")
+    ap.add_argument("--async-coherent", type=int, default=None, choices=[0, 1],
+                    help="ASYNC: device-coherent loads of C' and Sigma' (1) or cached loads (0, library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -169,7 +170,8 @@ def main():
     print(f"[bench] generated {desc}: n={g.n} arcs={g.nnz} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     off, idx, w = lv.graph_tensors(g, "cuda:0")
     mode = lv.ASYNC if args.mode == "async" else lv.SYNC
-    L = lv.Louvain(off, idx, w, mode=mode, async_coherent=args.async_coherent)
+    extra = {} if args.async_coherent is None else {"async_coherent": args.async_coherent}
+    L = lv.Louvain(off, idx, w, mode=mode, **extra)
     dt, q, st = timed_runs(L, args.steps, args.warmup)
     print(f"[bench] {args.steps} runs, {dt * 1e3:.2f} ms/run, Q={q:.5f}, passes={st.passes} "
           f"iterations={st.iterations} communities={st.communities}", file=sys.stderr, flush=True)
@@ -237,7 +239,8 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "vertices": g.n, "arcs": g.nnz, "undirected_edges": g.nnz // 2,
-                   "mode": args.mode, "pruner": "flags", "async_coherent": args.async_coherent, "modularity": round(q, 6), "passes": st.passes,
+                   "mode": args.mode, "pruner": "flags", "async_coherent": L.params.async_coherent,
+                   "async_min_label": L.params.async_min_label, "modularity": round(q, 6), "passes": st.passes,
                    "iterations": st.iterations, "communities": st.communities,
                    "vertices_evaluated": st.vertices_evaluated, "arcs_scanned": st.arcs_scanned,
                    "undirected_Medges_per_s": round(g.nnz / 2 / dt / 1e6, 2)},

@@ -123,10 +123,11 @@ typedef struct {
      * bucket use global-memory hash tables.  Used by tests to force paths. */
     int32_t bucket_max_degree[8];
     int32_t agg_bucket_max[8];
-    /* ASYNC only: 1 (default) makes reads and writes of C' and Sigma' in the
+    /* ASYNC only: 1 makes reads and writes of C' and Sigma' in the
      * local-moving kernels device-coherent, so a workgroup sees moves made by
-     * workgroups on other chiplets within the same launch; 0 uses cached
-     * loads (moves become visible at kernel boundaries). */
+     * workgroups on other chiplets within the same launch; 0 (default) uses
+     * cached loads (moves become visible at kernel boundaries, i.e. from one
+     * slice to the next). */
     int32_t async_coherent;
     /* Order in which degree buckets are launched within an iteration:
      * 0 = low degree first (default), 1 = high degree first. */
@@ -141,7 +142,18 @@ typedef struct {
     int32_t async_slice_iters;
     /* LEARNED pruner only: exit test of a sweep (0 strict, 1 tolerance). */
     int32_t guard_tolerance;
-    int32_t reserved[3];
+    /* ASYNC only: at least this many queued vertices per slice (default 32);
+     * an iteration uses min(async_slices, queued / async_slice_min) slices. */
+    int32_t async_slice_min;
+    /* ASYNC only: the hubs (vertices above the largest LDS bucket) of an
+     * iteration are processed in this many id-ordered groups, group k right
+     * after slice floor((k + 1) * slices / groups) - 1; 0 = one group per
+     * slice (default). */
+    int32_t async_hub_groups;
+    /* ASYNC only: 1 = a vertex alone in its community does not join another
+     * single-vertex community of larger id (the pair merges the other way),
+     * which prevents concurrent swaps of singletons; 1 = on (default). */
+    int32_t async_min_label;
     const float* pruner_weights; /* LEARNED: device, LOUVAIN_MLP_PARAMS floats, read during louvain_run */
     double pruner_threshold;     /* LEARNED: theta */
 } louvain_params;

@@ -49,7 +49,8 @@ class LouvainParams(ctypes.Structure):
                 ("bucket_max_degree", ctypes.c_int32 * 8), ("agg_bucket_max", ctypes.c_int32 * 8),
                 ("async_coherent", ctypes.c_int32), ("bucket_order", ctypes.c_int32),
                 ("async_slices", ctypes.c_int32), ("async_slice_iters", ctypes.c_int32),
-                ("guard_tolerance", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("guard_tolerance", ctypes.c_int32), ("async_slice_min", ctypes.c_int32),
+                ("async_hub_groups", ctypes.c_int32), ("async_min_label", ctypes.c_int32),
                 ("pruner_weights", ctypes.c_void_p), ("pruner_threshold", ctypes.c_double)]
 
 

@@ -13,8 +13,8 @@ LIB = os.path.join(OUT_DIR, "liblouvain_hip.so")
 SOURCES = ["lv_scan.hip", "lv_move.hip", "lv_aggr.hip", "lv_learn.hip", "lv_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# Packed FP32 instructions are disabled for all device code (no float math in
-# this library, but the flag keeps the compiler from emitting them anyway).
+# Packed FP32 instructions are disabled for all device code (the learned
+# pruner's FP32 arithmetic must not be turned into them).
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

@@ -41,7 +41,7 @@ inline uint64_t next_pow2(uint64_t x) {
 }
 
 struct Layout {
-    size_t ctl, seg, C, Cp, K, Sig, mark, vbucket, blist, qa, qb, movers, hcaps, hpre;
+    size_t ctl, seg, C, Cp, K, Sig, mark, vbucket, blist, qa, qb, sdec, hcaps, hpre;
     size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
     size_t hidx, hw, sup_off[2], sup_idx[2], sup_w[2], pool_keys, pool_vals, scan;
     size_t md, mpos, bnch, bchpre, bitmaps, gdec, blkcnt, blkoff;
@@ -66,7 +66,7 @@ bool make_layout(int64_t n, int64_t m, Layout* L) {
     L->blist = take(N * 4);
     L->qa = take(N * 4);
     L->qb = take(N * 4);
-    L->movers = take(2 * N * 4);
+    L->sdec = take(N * 4);
     L->hcaps = take((N + 1) * 8);
     L->hpre = take((N + 1) * 8);
     L->used = take((N + 1) * 4);
@@ -302,11 +302,14 @@ void louvain_params_default(louvain_params* p) {
     p->mode = LOUVAIN_ASYNC;
     p->pruner = LOUVAIN_PRUNE_FLAGS;
     p->validate = 1;
-    p->async_coherent = 1;
+    p->async_coherent = 0;
     p->bucket_order = 0;
     p->async_slices = 64;
     p->async_slice_iters = 0;
     p->guard_tolerance = 1;
+    p->async_slice_min = 32;
+    p->async_hub_groups = 0;
+    p->async_min_label = 1;
     p->pruner_weights = nullptr;
     p->pruner_threshold = 0.5;
 }
@@ -338,7 +341,8 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
         p->agg_num < 0 || p->pick_less < 0 || (p->mode != LOUVAIN_ASYNC && p->mode != LOUVAIN_SYNC) ||
         (p->pruner != LOUVAIN_PRUNE_NONE && p->pruner != LOUVAIN_PRUNE_FLAGS &&
          p->pruner != LOUVAIN_PRUNE_LEARNED) ||
-        (p->guard_tolerance != 0 && p->guard_tolerance != 1))
+        (p->guard_tolerance != 0 && p->guard_tolerance != 1) || p->async_slices < 0 || p->async_slice_min < 0 ||
+        p->async_hub_groups < 0)
         return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid parameter value");
     if (p->pruner == LOUVAIN_PRUNE_LEARNED && !p->pruner_weights)
         return fail(nullptr, LOUVAIN_ERR_INVALID, "the learned pruner needs pruner_weights");
@@ -590,11 +594,12 @@ louvain_status Runner::run() {
             a.W = W;
             a.wide = wide;
             a.pl = pl;
+            a.min_label = P.async_min_label;
             a.prune = prune;
             a.stamp_next = stamp_next;
             a.mark = mark;
             a.ctl = ctl();
-            a.movers = at<int32_t>(Y.movers);
+            a.sdec = at<int32_t>(Y.sdec);
             a.vbucket = vb;
             a.hub_list = hub_list;
             a.hub_pre = hpre;
@@ -634,17 +639,25 @@ louvain_status Runner::run() {
             };
             // ASYNC: the iteration runs as ns slices in vertex-id order (each
             // bucket's queue is sorted by id; slice sl takes the sl-th share of
-            // every bucket), at least ~32 queued vertices per slice.
+            // every bucket), at least async_slice_min queued vertices per slice.
             int64_t queued = 0;
             for (int b = 0; b < NBT; b++) queued += counts[b];
             const bool slice_now = P.async_slice_iters <= 0 || t < P.async_slice_iters;
             int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
-            ns = (int)std::max<int64_t>(1, std::min<int64_t>(ns, queued / 32));
+            ns = (int)std::max<int64_t>(1, std::min<int64_t>(ns, queued / std::max(1, P.async_slice_min)));
+            // hub groups: group k covers the static hub positions [k*nhub/hg, (k+1)*nhub/hg)
+            // and runs with slice due(k) = (k+1)*ns/hg - 1
+            const int hg = (!sync && P.async_hub_groups > 0) ? std::min(P.async_hub_groups, ns) : ns;
             for (int sl = 0; sl < ns; sl++) {
                 auto lo_of = [&](int b) { return (int32_t)((int64_t)counts[b] * sl / ns); };
                 auto hi_of = [&](int b) { return (int32_t)((int64_t)counts[b] * (sl + 1) / ns); };
-                const int32_t h_lo = (int32_t)((int64_t)nhub * sl / ns), h_hi = (int32_t)((int64_t)nhub * (sl + 1) / ns);
-                if (P.bucket_order && hubs_now) hubs_range(h_lo, h_hi, true, !sync);
+                int32_t h_lo = 0, h_hi = 0;  // hub positions due with this slice
+                for (int k = 0; k < hg; k++)
+                    if ((int)(((int64_t)(k + 1) * ns) / hg) - 1 == sl) {
+                        if (h_hi == h_lo) h_lo = (int32_t)((int64_t)nhub * k / hg);
+                        h_hi = (int32_t)((int64_t)nhub * (k + 1) / hg);
+                    }
+                if (P.bucket_order && hubs_now && h_hi > h_lo) hubs_range(h_lo, h_hi, true, !sync);
                 FusedLists f{};
                 f.blk_pre[0] = 0;
                 for (int b = 0; b < 4; b++) {
@@ -662,10 +675,10 @@ louvain_status Runner::run() {
                         timed(H, K_MOVE4, 0, [&] { launch_move(LM, 4, mode, a, cur_list + csegs[4] + lo, hi - lo, s); });
                     }
                 }
-                if (!P.bucket_order && hubs_now) hubs_range(h_lo, h_hi, true, !sync);
+                if (!P.bucket_order && hubs_now && h_hi > h_lo) hubs_range(h_lo, h_hi, true, !sync);
             }
             if (sync) {
-                timed(H, K_SYNC_APPLY, 0, [&] { launch_sync_apply(L, a, s); });
+                timed(H, K_SYNC_APPLY, 0, [&] { launch_sync_apply(L, a, cur_list, csegs[NBT], s); });
                 if (hubs_now) hubs_range(0, nhub, false, true);
             }
             if (learn) launch_learn_label(H->smp_buf, smp_lo, smp_hi, f_moved, stamp_next, s);

@@ -31,8 +31,7 @@ constexpr int STRIPES = 32;
 struct Ctl {
     // ---- zeroed before every local-moving iteration
     int32_t qcount[MAX_BUCKETS];  // next-iteration queue sizes, per move bucket
-    int32_t movers;               // SYNC: number of (vertex, target) pairs recorded
-    int32_t pad0;
+    int32_t pad0[2];
     u64 s_lo[STRIPES];            // 128-bit sums of applied gains (two's complement)
     u64 s_hi[STRIPES];
     u64 moves[STRIPES];           // moves applied

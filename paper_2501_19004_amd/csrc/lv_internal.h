@@ -51,11 +51,12 @@ struct MoveArgs {
     i64 W;                // total weight (2m)
     int32_t wide;         // 1: 128-bit gain arithmetic
     int32_t pl;           // Pick-Less active this iteration
+    int32_t min_label;    // ASYNC: singletons join only singletons of smaller id
     int32_t prune;        // 1: stamp neighbours of movers for the next iteration
     uint32_t stamp_next;  // stamp marking membership of the next iteration's queue
     uint32_t* mark;
     Ctl* ctl;
-    int32_t* movers;      // SYNC: (vertex, target) pairs
+    int32_t* sdec;        // SYNC: per vertex of the queue, its decided target or -1
     int32_t bucket;       // bucket id for per-bucket counters
     const uint8_t* vbucket;
     // hub path (static hub list of the pass, ascending vertex id)
@@ -146,7 +147,7 @@ void launch_hub_insert(const LevelView& L, int mode, const MoveArgs& a, int64_t 
 void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s);
 void launch_hub_mark(const LevelView& L, const MoveArgs& a, int64_t nchunks, hipStream_t s);
 void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const FusedLists& f, hipStream_t s);
-void launch_sync_apply(const LevelView& L, const MoveArgs& a, hipStream_t s);
+void launch_sync_apply(const LevelView& L, const MoveArgs& a, const int32_t* list, int64_t count, hipStream_t s);
 void launch_learn_filter(const FilterArgs& f, int off64, hipStream_t s);
 void launch_learn_label(float* samples, int64_t lo, int64_t hi, const uint32_t* moved, uint32_t itag,
                         hipStream_t s);

@@ -53,22 +53,6 @@ void dispatch_types(const LevelTypes& t, Fn&& fn) {
 
 inline unsigned blocks_for(int64_t items, int per_block) { return (unsigned)((items + per_block - 1) / per_block); }
 
-// Wave-aggregated append of (x, y) pairs to a flat array.
-__device__ __forceinline__ void wave_append_pair(bool want, int32_t x, int32_t y, int32_t* out, int32_t* count) {
-    const int lane = __lane_id();
-    u64 m = __ballot(want);
-    if (!m) return;
-    int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(count, __popcll(m));
-    base = __shfl(base, leader);
-    if (want) {
-        int r = base + __popcll(m & ((1ull << lane) - 1ull));
-        out[2 * (int64_t)r] = x;
-        out[2 * (int64_t)r + 1] = y;
-    }
-}
-
 // ---------------------------------------------------------- group reductions
 // Reductions over a group of G lanes; for G > 64 the group is the whole
 // workgroup and the cross-wave step goes through LDS.
@@ -257,15 +241,33 @@ __device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* key
     int32_t bd = EMPTY_KEY;
     i64 bv = 0, kic = 0, nd = 0;
     const int64_t span = list ? nlist : cap;
-    for (int64_t k = lane; k < span; k += G) {
-        const int64_t s = list ? (int64_t)list[k] : k;
-        const int32_t d = keys[s];
-        if (d == EMPTY_KEY) continue;
-        ++nd;
-        const i64 v = (i64)vals[s];
-        if (d == c) { kic = v; continue; }
-        const KeyT key = (KeyT)a.W * v - (KeyT)Ki * ld_s<MODE>(&a.Sig[d]);
-        if (bd == EMPTY_KEY || better(key, d, bk, bd)) { bk = key; bd = d; bv = v; }
+    // U slots per round: their Sigma gathers are issued together.
+    constexpr int U = 4;
+    for (int64_t k0 = lane; k0 < span; k0 += U * G) {
+        int32_t dd[U];
+        i64 vv[U], ss[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t k = k0 + (int64_t)u * G;
+            dd[u] = EMPTY_KEY;
+            vv[u] = 0;
+            if (k < span) {
+                const int64_t s = list ? (int64_t)list[k] : k;
+                dd[u] = keys[s];
+                vv[u] = (i64)vals[s];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) ss[u] = (dd[u] != EMPTY_KEY && dd[u] != c) ? ld_s<MODE>(&a.Sig[dd[u]]) : 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int32_t d = dd[u];
+            if (d == EMPTY_KEY) continue;
+            ++nd;
+            if (d == c) { kic = vv[u]; continue; }
+            const KeyT key = (KeyT)a.W * vv[u] - (KeyT)Ki * ss[u];
+            if (bd == EMPTY_KEY || better(key, d, bk, bd)) { bk = key; bd = d; bv = vv[u]; }
+        }
     }
     // Lanes without a candidate must not win: give them the smallest key.
     if (bd == EMPTY_KEY) bk = (sizeof(KeyT) == 8) ? (KeyT)INT64_MIN : (KeyT)(((i128)1) << 127);
@@ -277,7 +279,14 @@ __device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* key
         const KeyT stay = (KeyT)a.W * kic - (KeyT)Ki * (Sc - Ki);
         const KeyT gk = bk - stay;
         r.positive = gk > 0;
-        if (gk > 0 && (!a.pl || bd < c)) { r.target = bd; r.kid = bv; r.gain = (i128)gk; }
+        bool ok = gk > 0 && (!a.pl || bd < c);
+        if constexpr (MODE != M_SYNC) {
+            // i alone in c, d a single-vertex community of larger id: let d's vertex come to c instead
+            if (ok && a.min_label && bd > c && Sc == Ki && ld_c<MODE>(&a.Cp[bd]) == bd &&
+                ld_s<MODE>(&a.Sig[bd]) == a.K[bd])
+                ok = false;
+        }
+        if (ok) { r.target = bd; r.kid = bv; r.gain = (i128)gk; }
     }
     return r;
 }
@@ -382,11 +391,22 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
         o0 = (i64)g.off[i];
         o1 = (i64)g.off[i + 1];
     }
-    for (i64 e = o0 + lane; e < o1; e += G) {
-        const int32_t j = g.idx[e];
-        if (j == i) continue;
-        const int32_t d = ld_c<MODE>(&a.Cp[j]);
-        table_add<AccT>(keys, vals, CAP - 1, hash_slot<L2C>(d), d, (AccT)g.weight(e));
+    // U arcs per round: their index loads, then their C' gathers, are issued together.
+    constexpr int U = 4;
+    for (i64 e0 = o0 + lane; e0 < o1; e0 += U * G) {
+        int32_t jj[U], dd[U];
+        AccT ww[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const i64 e = e0 + (i64)u * G;
+            jj[u] = e < o1 ? g.idx[e] : i;
+            ww[u] = e < o1 ? (AccT)g.weight(e) : (AccT)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) dd[u] = jj[u] != i ? ld_c<MODE>(&a.Cp[jj[u]]) : EMPTY_KEY;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (dd[u] != EMPTY_KEY) table_add<AccT>(keys, vals, CAP - 1, hash_slot<L2C>(dd[u]), dd[u], ww[u]);
     }
     group_sync<G>();
 
@@ -396,7 +416,7 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
 
     if (a.learn && active && lane == 0) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
-        wave_append_pair(lane == 0 && dcs.target >= 0, i, dcs.target, a.movers, &a.ctl->movers);
+        if (lane == 0 && active) a.sdec[i] = dcs.target;
     } else {
         int32_t t = -1;
         if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, i, c, Ki, dcs)) t = dcs.target;
@@ -573,11 +593,7 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
     const i64 deg = (i64)off[v + 1] - (i64)off[v];
     if (tid == 0) {
         if constexpr (MODE == M_SYNC) {
-            if (dcs.target >= 0) {
-                const int32_t r = atomicAdd(&a.ctl->movers, 1);
-                a.movers[2 * (int64_t)r] = v;
-                a.movers[2 * (int64_t)r + 1] = dcs.target;
-            }
+            a.sdec[v] = dcs.target;
         } else {
             if (dcs.target >= 0) apply_async<MODE>(a, v, c, Ki, dcs);
         }
@@ -602,26 +618,35 @@ __global__ void __launch_bounds__(1024) k_hub_mark(MoveArgs a) {
     for (i64 e = e0 + threadIdx.x; e < e1; e += 1024) mark_one(a, v, a.idx[e]);
 }
 
-// SYNC: apply the recorded decisions together, then stamp the movers'
-// neighbours for the next iteration.  One wave per mover.
+// SYNC: apply the recorded decisions of the iteration's queue together, then
+// stamp the movers' neighbours for the next iteration (hubs' rows are
+// stamped by the chunked hub marking).  One wave per 64 queue entries: each
+// lane applies its own vertex's move; the wave then walks each mover's row.
 template <typename OffT>
-__global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a) {
-    const int32_t nm = *(volatile int32_t*)&a.ctl->movers;
+__global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a, const int32_t* __restrict__ list, int64_t count) {
     const int lane = threadIdx.x % WAVE;
-    const int64_t nw = (int64_t)gridDim.x * (256 / WAVE);
+    const int64_t k = ((int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE) * WAVE + lane;
     const Graph<OffT, 0> g{(const OffT*)a.off, a.idx, nullptr};
-    for (int64_t m = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE; m < nm; m += nw) {
-        const int32_t i = a.movers[2 * m], d = a.movers[2 * m + 1];
-        if (lane == 0) {
-            const int32_t c = a.Cp[i];
-            const i64 Ki = a.K[i];
-            atomicAdd((u64*)&a.Sig[c], (u64)(-Ki));
-            atomicAdd((u64*)&a.Sig[d], (u64)Ki);
-            a.Cp[i] = d;
-            if (a.learn) a.f_moved[i] = a.itag;
+    int32_t v = -1, d = -1;
+    if (k < count) {
+        v = list[k];
+        d = a.sdec[v];
+        if (d >= 0) {
+            const int32_t c = a.Cp[v];
+            const i64 Kv = a.K[v];
+            atomicAdd((u64*)&a.Sig[c], (u64)(-Kv));
+            atomicAdd((u64*)&a.Sig[d], (u64)Kv);
+            a.Cp[v] = d;
+            if (a.learn) a.f_moved[v] = a.itag;
         }
-        if ((a.prune || a.learn) && a.vbucket[i] != NB_MOVE)
-            mark_neighbours<WAVE>(a, g, i, (i64)g.off[i], (i64)g.off[i + 1], lane);
+    }
+    if (!(a.prune || a.learn)) return;
+    u64 todo = __ballot(d >= 0 && a.vbucket[v] != NB_MOVE);
+    while (todo) {
+        const int b = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int32_t m = __shfl(v, b, WAVE);
+        mark_neighbours<WAVE>(a, g, m, (i64)g.off[m], (i64)g.off[m + 1], lane);
     }
 }
 
@@ -766,10 +791,11 @@ void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const Fu
     });
 }
 
-void launch_sync_apply(const LevelView& L, const MoveArgs& a, hipStream_t s) {
-    const unsigned grid = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (L.n + 3) / 4));
-    if (L.t.off64) k_sync_apply<int64_t><<<grid, 256, 0, s>>>(a);
-    else k_sync_apply<int32_t><<<grid, 256, 0, s>>>(a);
+void launch_sync_apply(const LevelView& L, const MoveArgs& a, const int32_t* list, int64_t count, hipStream_t s) {
+    if (count <= 0) return;
+    const unsigned grid = (unsigned)((count + 255) / 256);
+    if (L.t.off64) k_sync_apply<int64_t><<<grid, 256, 0, s>>>(a, list, count);
+    else k_sync_apply<int32_t><<<grid, 256, 0, s>>>(a, list, count);
 }
 
 }  // namespace lv

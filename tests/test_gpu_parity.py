@@ -161,18 +161,36 @@ def test_async_quality_planted(name, seed):
     assert q >= qo - 0.002, (q, qo)
 
 
+@pytest.mark.parametrize("coherent,min_label", [(0, 1), (1, 1)], ids=["default", "coherent"])
 @pytest.mark.parametrize("make", [lambda: gg.rmat(14, 16, seed=5), lambda: gg.grid(128, 128, seed=6),
                                   lambda: gg.sbm_degree(20000, 32, 16.0, seed=7, wmin=1, wmax=4),
-                                  lambda: gg.rmat(12, 8, seed=8, wmax=9)],
-                         ids=["rmat14", "grid128", "sbm20k", "rmat12w"])
-def test_async_quality(make):
+                                  lambda: gg.rmat(12, 8, seed=8, wmax=9), lambda: gg.rmat(17, 16, seed=17),
+                                  lambda: gg.grid(512, 512, seed=9)],
+                         ids=["rmat14", "grid128", "sbm20k", "rmat12w", "rmat17", "grid512"])
+def test_async_quality(make, coherent, min_label):
     g = make()
-    memb, (q, num, den), _, _, _ = run_gpu(g, lv.ASYNC, trace=False)
+    memb, (q, num, den), _, _, _ = run_gpu(g, lv.ASYNC, trace=False, async_coherent=coherent,
+                                           async_min_label=min_label)
     qo = oracle.modularity(g, oracle.louvain(g).membership)
     assert (num, den) == oracle.modularity_parts(g, memb)
     assert sorted(set(memb.tolist())) == list(range(int(memb.max()) + 1))
     print(f"Q_gpu - Q_oracle = {q - qo:+.5f}")
     assert q >= qo - 0.002, (q, qo)
+
+
+@pytest.mark.parametrize("make", [lambda: gg.rmat(14, 16, seed=5), lambda: gg.grid(128, 128, seed=6)],
+                         ids=["rmat14", "grid128"])
+@pytest.mark.parametrize("slices,hub_groups", [(1, 0), (64, 1), (256, 8)])
+def test_async_variants_valid(make, slices, hub_groups):
+    """Other ASYNC settings (no minimum-label rule, one slice, grouped hubs):
+    the result is a valid partition whose exact modularity matches the
+    oracle's evaluation of it; quality is not bounded for these."""
+    g = make()
+    memb, (q, num, den), _, _, st = run_gpu(g, lv.ASYNC, trace=False, async_min_label=0, async_slices=slices,
+                                            async_hub_groups=hub_groups)
+    assert (num, den) == oracle.modularity_parts(g, memb)
+    assert sorted(set(memb.tolist())) == list(range(st.communities))
+    assert q > 0
 
 
 def test_invalid_graph_rejected():
