@@ -444,22 +444,88 @@ __global__ void k_final_lookup(int32_t* __restrict__ C, int64_t n0, const int32_
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n0) C[v] = newid[Cp[C[v]]];
 }
-template <typename OffT>
-__global__ void k_comm_count(const OffT* __restrict__ off, int64_t n, const int32_t* __restrict__ Cp,
-                             int32_t* __restrict__ cnt, int64_t* __restrict__ cdeg) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const int32_t c = Cp[v];
-    atomicAdd(&cnt[c], 1);
-    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-    if (deg) atomicAdd((u64*)&cdeg[c], (u64)deg);
+// Community sizes, total degrees and member lists.  Large communities hold
+// many vertices, so a global atomic per vertex would serialise on their
+// counters; instead every block first combines its tile of CT_TILE vertices
+// in an LDS table keyed by community and issues one global atomic per
+// (block, community).
+constexpr int CT_TPB = 256;
+constexpr int CT_PER = 4;
+constexpr int CT_TILE = CT_TPB * CT_PER;
+constexpr int CT_CAP = 2 * CT_TILE;  // >= 2 * distinct communities of a tile
+constexpr int CT_L2C = 11;
+static_assert((1 << CT_L2C) == CT_CAP, "table size");
+
+// Slot of key c in the tile table (inserting it if absent).
+__device__ __forceinline__ uint32_t ct_slot(int32_t* keys, int32_t c) {
+    uint32_t s = hash_slot<CT_L2C>(c);
+    for (uint32_t step = 1;; ++step) {
+        const int32_t k = *(volatile int32_t*)&keys[s];
+        if (k == c) return s;
+        if (k == EMPTY_KEY) {
+            const int32_t old = atomicCAS(&keys[s], EMPTY_KEY, c);
+            if (old == EMPTY_KEY || old == c) return s;
+        }
+        s = (s + step) & (CT_CAP - 1);
+    }
 }
-__global__ void k_comm_fill(int64_t n, const int32_t* __restrict__ Cp, const int32_t* __restrict__ coff,
-                            int32_t* __restrict__ cursor, int32_t* __restrict__ members) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const int32_t c = Cp[v];
-    members[coff[c] + atomicAdd(&cursor[c], 1)] = (int32_t)v;
+
+template <typename OffT>
+__global__ void __launch_bounds__(CT_TPB) k_comm_count(const OffT* __restrict__ off, int64_t n,
+                                                       const int32_t* __restrict__ Cp, int32_t* __restrict__ cnt,
+                                                       int64_t* __restrict__ cdeg) {
+    __shared__ int32_t s_keys[CT_CAP];
+    __shared__ int32_t s_cnt[CT_CAP];
+    __shared__ u64 s_deg[CT_CAP];
+    for (int k = threadIdx.x; k < CT_CAP; k += CT_TPB) { s_keys[k] = EMPTY_KEY; s_cnt[k] = 0; s_deg[k] = 0; }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE;
+    for (int q = 0; q < CT_PER; q++) {
+        const int64_t v = base + q * CT_TPB + threadIdx.x;
+        if (v >= n) break;
+        const uint32_t sl = ct_slot(s_keys, Cp[v]);
+        atomicAdd(&s_cnt[sl], 1);
+        const u64 deg = (u64)((int64_t)off[v + 1] - (int64_t)off[v]);
+        if (deg) atomicAdd(&s_deg[sl], deg);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < CT_CAP; k += CT_TPB) {
+        const int32_t c = s_keys[k];
+        if (c == EMPTY_KEY) continue;
+        atomicAdd(&cnt[c], s_cnt[k]);
+        if (s_deg[k]) atomicAdd((u64*)&cdeg[c], s_deg[k]);
+    }
+}
+
+__global__ void __launch_bounds__(CT_TPB) k_comm_fill(int64_t n, const int32_t* __restrict__ Cp,
+                                                      const int32_t* __restrict__ coff, int32_t* __restrict__ cursor,
+                                                      int32_t* __restrict__ members) {
+    __shared__ int32_t s_keys[CT_CAP];
+    __shared__ int32_t s_cnt[CT_CAP];
+    __shared__ int32_t s_pos[CT_CAP];
+    for (int k = threadIdx.x; k < CT_CAP; k += CT_TPB) { s_keys[k] = EMPTY_KEY; s_cnt[k] = 0; }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE;
+    uint32_t slot[CT_PER];
+    for (int q = 0; q < CT_PER; q++) {
+        const int64_t v = base + q * CT_TPB + threadIdx.x;
+        slot[q] = 0xffffffffu;
+        if (v >= n) continue;
+        slot[q] = ct_slot(s_keys, Cp[v]);
+        atomicAdd(&s_cnt[slot[q]], 1);
+    }
+    __syncthreads();
+    // one global reservation per (block, community)
+    for (int k = threadIdx.x; k < CT_CAP; k += CT_TPB) {
+        const int32_t c = s_keys[k];
+        if (c != EMPTY_KEY) s_pos[k] = coff[c] + atomicAdd(&cursor[c], s_cnt[k]);
+    }
+    __syncthreads();
+    for (int q = 0; q < CT_PER; q++) {
+        if (slot[q] == 0xffffffffu) continue;
+        const int64_t v = base + q * CT_TPB + threadIdx.x;
+        members[atomicAdd(&s_pos[slot[q]], 1)] = (int32_t)v;
+    }
 }
 // Aggregation bucket of community c: by the bound min(total degree, ncom)
 // on its distinct neighbours; communities with more than BIG_ARCS arcs, or
@@ -578,13 +644,13 @@ void launch_final_lookup(int32_t* C, int64_t n0, const int32_t* Cp, const int32_
 void launch_comm_count(const LevelView& L, const int32_t* Cp, int32_t* cnt, int64_t* cdeg, hipStream_t s) {
     if (L.n <= 0) return;
     if (L.t.off64)
-        k_comm_count<int64_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, Cp, cnt, cdeg);
+        k_comm_count<int64_t><<<blocks_for(L.n, CT_TILE), CT_TPB, 0, s>>>((const int64_t*)L.off, L.n, Cp, cnt, cdeg);
     else
-        k_comm_count<int32_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, Cp, cnt, cdeg);
+        k_comm_count<int32_t><<<blocks_for(L.n, CT_TILE), CT_TPB, 0, s>>>((const int32_t*)L.off, L.n, Cp, cnt, cdeg);
 }
 void launch_comm_fill(int64_t n, const int32_t* Cp, const int32_t* coff, int32_t* cursor, int32_t* members,
                       hipStream_t s) {
-    if (n > 0) k_comm_fill<<<blocks_for(n, 256), 256, 0, s>>>(n, Cp, coff, cursor, members);
+    if (n > 0) k_comm_fill<<<blocks_for(n, CT_TILE), CT_TPB, 0, s>>>(n, Cp, coff, cursor, members);
 }
 void bucketize_communities(int64_t ncom, const int64_t* hoff, int64_t bound_cap, const Buckets& B, int32_t* rowlen,
                            int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,

@@ -121,12 +121,12 @@ struct KRec {
 
 enum KName { K_MOVE_FUSED = 0, K_MOVE1, K_MOVE2, K_MOVE3, K_MOVE4, K_MOVE_HUB, K_SYNC_APPLY, K_PASS_INIT, K_AGG_PREP,
              K_AGG0, K_AGG1, K_AGG2, K_AGG3, K_AGG_BIG_INSERT, K_AGG_BIG_EXTRACT, K_COMPACT, K_QUEUE, K_HUB_MARK,
-             K_LEARN_FILTER, K_COUNT };
+             K_LEARN_FILTER, K_HUB_DECIDE, K_COUNT };
 const char* KNAMES[K_COUNT] = {"move_b0_3", "move_unused1", "move_unused2", "move_unused3", "move_b4", "move_hub",
                                "sync_apply",
                                "pass_init", "aggregate_prep", "aggregate_b0", "aggregate_b1", "aggregate_b2",
                                "aggregate_b3", "aggregate_big_insert", "aggregate_big_extract", "compact",
-                               "queue_build", "hub_mark", "learn_filter"};
+                               "queue_build", "hub_mark", "learn_filter", "hub_decide"};
 
 }  // namespace
 
@@ -628,11 +628,10 @@ louvain_status Runner::run() {
                     a.g_lo = lo;
                     a.g_hi = hi;
                     const int64_t nchunks = hch_pre[hi] - hch_pre[lo];
-                    if (decide_phase)
-                        timed(H, K_MOVE_HUB, 0, [&] {
-                            launch_hub_insert(LM, mode, a, nchunks, s);
-                            launch_hub_decide(LM, mode, a, s);
-                        });
+                    if (decide_phase) {
+                        timed(H, K_MOVE_HUB, 0, [&] { launch_hub_insert(LM, mode, a, nchunks, s); });
+                        timed(H, K_HUB_DECIDE, 0, [&] { launch_hub_decide(LM, mode, a, s); });
+                    }
                     if (mark_phase && (prune || learn))
                         timed(H, K_HUB_MARK, 0, [&] { launch_hub_mark(L, a, nchunks, s); });
                 }
