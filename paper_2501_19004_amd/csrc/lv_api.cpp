@@ -61,7 +61,7 @@ bool make_layout(int64_t n, int64_t m, Layout* L) {
     L->Cp = take(N * 4);
     L->K = take(N * 8);
     L->Sig = take(N * 8);
-    L->mark = take(N * 4);
+    L->mark = take(2 * N);  // two byte flag arrays: this iteration's queue, the next one's
     L->vbucket = take(N);
     L->blist = take(N * 4);
     L->qa = take(N * 4);
@@ -308,7 +308,7 @@ void louvain_params_default(louvain_params* p) {
     p->async_slice_iters = 0;
     p->guard_tolerance = 1;
     p->async_slice_min = 32;
-    p->async_hub_groups = 0;
+    p->async_hub_groups = 16;
     p->async_min_label = 1;
     p->pruner_weights = nullptr;
     p->pruner_threshold = 0.5;
@@ -384,7 +384,7 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
     }
     // zero control block, pruning stamps and moved-iteration tags
     if (hipMemsetAsync(h->ctl(), 0, sizeof(Ctl), h->stream) != hipSuccess ||
-        hipMemsetAsync(h->at<uint32_t>(lay.mark), 0, (size_t)std::max<int64_t>(g->n, 1) * 4, h->stream) !=
+        hipMemsetAsync(h->at<uint8_t>(lay.mark), 0, (size_t)std::max<int64_t>(g->n, 1) * 2, h->stream) !=
             hipSuccess ||
         hipMemsetAsync(h->at<uint32_t>(lay.f_moved), 0, (size_t)std::max<int64_t>(g->n, 1) * 4, h->stream) !=
             hipSuccess) {
@@ -493,7 +493,7 @@ louvain_status Runner::run() {
     int32_t* Cp = at<int32_t>(Y.Cp);
     i64* K = at<i64>(Y.K);
     i64* Sig = at<i64>(Y.Sig);
-    uint32_t* mark = at<uint32_t>(Y.mark);
+    uint8_t* flags = at<uint8_t>(Y.mark);
     uint8_t* vb = at<uint8_t>(Y.vbucket);
     int32_t* blist = at<int32_t>(Y.blist);
     int32_t* qbuf[2] = {at<int32_t>(Y.qa), at<int32_t>(Y.qb)};
@@ -526,7 +526,7 @@ louvain_status Runner::run() {
         int32_t bcount[MAX_BUCKETS] = {};
         timed(H, K_PASS_INIT, 0, [&] {
             launch_classify(L, H->mb, vb, Cp, K, Sig, s);
-            bucketize_vertices(n, vb, mark, 0, 0, blkcnt, blkoff, blist, ctl()->bcount, scan, s);
+            bucketize_vertices(n, vb, nullptr, 0, blkcnt, blkoff, blist, ctl()->bcount, scan, s);
         });
         if ((st = readback(H, bcount, ctl()->bcount, NBT * sizeof(int32_t))) != LOUVAIN_OK) return st;
         int64_t segs[MAX_BUCKETS + 1];
@@ -581,7 +581,10 @@ louvain_status Runner::run() {
             const int pl = P.pick_less > 0 && ((t + P.pick_less / 2) % P.pick_less) == 0;
             HIPCHK(H, hipMemsetAsync(ctl(), 0, CTL_ITER_BYTES, s));
             if (learn) HIPCHK(H, hipMemsetAsync(f_nm, 0, (size_t)n * 4, s));
-            const uint32_t stamp_next = ++H->stamp;
+            const uint32_t stamp_next = ++H->stamp;  // unique tag of this iteration
+            uint8_t* fnext = flags + (size_t)(stamp_next & 1) * (size_t)n0;
+            const uint8_t* fcur = flags + (size_t)((stamp_next + 1) & 1) * (size_t)n0;
+            if (prune) HIPCHK(H, hipMemsetAsync(fnext, 0, (size_t)n, s));
             if (sweep) H->st.sweeps++;
             int32_t* qnext = qbuf[qsel];
             MoveArgs a{};
@@ -596,8 +599,8 @@ louvain_status Runner::run() {
             a.pl = pl;
             a.min_label = P.async_min_label;
             a.prune = prune;
-            a.stamp_next = stamp_next;
-            a.mark = mark;
+            a.fnext = fnext;
+            a.fcur = fcur;
             a.ctl = ctl();
             a.sdec = at<int32_t>(Y.sdec);
             a.vbucket = vb;
@@ -605,7 +608,6 @@ louvain_status Runner::run() {
             a.hub_pre = hpre;
             a.hch_pre = hchpre;
             a.all_queued = (t == 0 || !prune || sweep) ? 1 : 0;
-            a.stamp_cur = stamp_next - 1;
             a.gdec = gdec;
             a.hub_keys = at<int32_t>(Y.pool_keys);
             a.hub_vals = at<void>(Y.pool_vals);
@@ -683,7 +685,7 @@ louvain_status Runner::run() {
             if (learn) launch_learn_label(H->smp_buf, smp_lo, smp_hi, f_moved, stamp_next, s);
             if (prune && !learn)
                 timed(H, K_QUEUE, 0, [&] {
-                    bucketize_vertices(n, vb, mark, stamp_next, 1, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
+                    bucketize_vertices(n, vb, fnext, 1, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
                 });
             // read back the iteration's striped totals
             Ctl* hc = (Ctl*)H->pinned;
@@ -744,8 +746,7 @@ louvain_status Runner::run() {
                     fa.itag_prev = stamp_next;
                     fa.pass = pass;
                     fa.t = t + 1;
-                    fa.mark = mark;
-                    fa.stamp = stamp_next;
+                    fa.flags = fnext;
                     fa.all = prune ? 0 : 1;
                     fa.learned = learned;
                     fa.weights = P.pruner_weights;
@@ -757,7 +758,7 @@ louvain_status Runner::run() {
                     timed(H, K_LEARN_FILTER, 0, [&] { launch_learn_filter(fa, L.t.off64, s); });
                     if (prune)
                         timed(H, K_QUEUE, 0, [&] {
-                            bucketize_vertices(n, vb, mark, stamp_next, 1, blkcnt, blkoff, qnext, ctl()->qcount,
+                            bucketize_vertices(n, vb, fnext, 1, blkcnt, blkoff, qnext, ctl()->qcount,
                                                scan, s);
                         });
                     HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));

@@ -14,8 +14,8 @@ namespace lv {
 // global-memory ("hub") path.
 constexpr int NB_MOVE = 5;
 constexpr int MOVE_G[NB_MOVE] = {8, 16, 64, 256, 1024};
-constexpr int MOVE_CAP[NB_MOVE] = {16, 64, 256, 2048, 8192};
-constexpr int MOVE_DEFAULT_MAX[NB_MOVE] = {8, 32, 128, 1024, 4096};
+constexpr int MOVE_CAP[NB_MOVE] = {16, 64, 256, 1024, 8192};
+constexpr int MOVE_DEFAULT_MAX[NB_MOVE] = {8, 32, 128, 512, 4096};
 constexpr int HUB_CH = 4096;    // arcs per hub insert chunk (one workgroup)
 constexpr int HUB_LCAP = 8192;  // LDS slots of a hub insert chunk
 
@@ -52,9 +52,9 @@ struct MoveArgs {
     int32_t wide;         // 1: 128-bit gain arithmetic
     int32_t pl;           // Pick-Less active this iteration
     int32_t min_label;    // ASYNC: singletons join only singletons of smaller id
-    int32_t prune;        // 1: stamp neighbours of movers for the next iteration
-    uint32_t stamp_next;  // stamp marking membership of the next iteration's queue
-    uint32_t* mark;
+    int32_t prune;        // 1: flag neighbours of movers for the next iteration
+    uint8_t* fnext;       // flags of the next iteration's queue (cleared before the iteration)
+    const uint8_t* fcur;  // flags of this iteration's queue
     Ctl* ctl;
     int32_t* sdec;        // SYNC: per vertex of the queue, its decided target or -1
     int32_t bucket;       // bucket id for per-bucket counters
@@ -64,8 +64,7 @@ struct MoveArgs {
     const int64_t* hub_pre;  // prefix of table capacities over the static list
     const int64_t* hch_pre;  // prefix of insert-chunk counts over the static list
     int32_t g_lo, g_hi;      // hubs of this launch group (their tables fit the pool together)
-    int32_t all_queued;      // 1: every hub is queued (first iteration or no pruning)
-    uint32_t stamp_cur;      // stamp of the current iteration's queue
+    int32_t all_queued;      // 1: every hub is queued (sweep, first iteration or no pruning)
     int32_t* gdec;           // per static hub: applied (ASYNC) or recorded (SYNC) target, or -1
     int32_t* hub_keys;
     void* hub_vals;
@@ -93,8 +92,7 @@ struct FilterArgs {
     const int32_t* nm;
     uint32_t itag_prev;   // tag of the iteration that just ended
     int32_t pass, t;      // of the iteration the queue is for
-    uint32_t* mark;
-    uint32_t stamp;       // flagged iff mark == stamp ...
+    uint8_t* flags;       // flagged iff flags[v] != 0 ...
     int32_t all;          // ... or, with all = 1, every vertex with an arc
     int32_t learned;      // apply the MLP
     const float* weights;
@@ -131,9 +129,9 @@ void iota_i32(int32_t* p, int64_t n, hipStream_t s);
 void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int32_t* Cp, i64* K, i64* Sig,
                      hipStream_t s);
 // Ordered partition of the level's vertices into NB_MOVE+1 bucket segments
-// (all vertices with arcs, or those whose mark equals `stamp`); bucket totals
+// (all vertices with arcs, or the flagged ones when use_flags); bucket totals
 // go to totals[0..NB_MOVE].  blkcnt/blkoff: (NB_MOVE+1) * bucket_blocks(n) (+1).
-void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint32_t* mark, uint32_t stamp, int use_mark,
+void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags,
                         int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
                         hipStream_t s);
 void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t count, i64* K, i64* Sig, Ctl* ctl,

@@ -76,9 +76,9 @@ __device__ __forceinline__ void stage_weights(float* s_w, const float* w) {
     __syncthreads();
 }
 
-// Filter of the next iteration's flagged vertices (mark == stamp, or every
+// Filter of the next iteration's flagged vertices (flags[v] set, or every
 // vertex with an arc when all = 1): features, MLP keep decision (a dropped
-// vertex is unstamped), sample recording.
+// vertex is unflagged), sample recording.
 template <typename OffT>
 __global__ void __launch_bounds__(256) k_learn_filter(FilterArgs f) {
     __shared__ float s_w[MLP_PARAMS];
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(256) k_learn_filter(FilterArgs f) {
     bool dropped = false;
     if (v < f.n) {
         const OffT* off = (const OffT*)f.off;
-        bool flagged = f.all || f.mark[v] == f.stamp;
+        bool flagged = f.all || f.flags[v];
         const int64_t deg = flagged ? (int64_t)off[v + 1] - (int64_t)off[v] : 0;
         flagged = flagged && deg > 0;
         const bool selected = flagged && f.per_mille > 0 && sample_selected(v, f.pass, f.t, f.per_mille);
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_learn_filter(FilterArgs f) {
             if (f.learned) {
                 keep = mlp_logit(s_w, x) >= f.zt;
                 if (!keep) {
-                    f.mark[v] = 0;
+                    f.flags[v] = 0;
                     dropped = true;
                 }
             }

@@ -15,9 +15,10 @@
 // processed by groups of G lanes per vertex (G = 8 .. 1024) with a private
 // open-addressing table of CAP slots in LDS, or -- above the largest LDS
 // bucket -- by one 1024-thread workgroup per vertex with a table in a global
-// memory pool.  Pruning flags are per-vertex stamps: a mover writes the next
-// iteration's stamp into its neighbours' slots, and the next queue is built
-// by an ordered compaction of the stamped vertices (lv_bucket.h).
+// memory pool.  Pruning flags are per-vertex bytes in two buffers (this
+// iteration's queue, the next one's): a mover sets its neighbours' next flags
+// with plain byte stores, and the next queue is built by an ordered
+// compaction of the flagged vertices (lv_bucket.h).
 #include <algorithm>
 
 #include "lv_bucket.h"
@@ -144,9 +145,8 @@ struct VBucket {
 };
 struct MarkBucket {
     const uint8_t* vb;
-    const uint32_t* mark;
-    uint32_t stamp;
-    __device__ __forceinline__ int operator()(int64_t v) const { return mark[v] == stamp ? (int)vb[v] : 255; }
+    const uint8_t* flags;
+    __device__ __forceinline__ int operator()(int64_t v) const { return flags[v] ? (int)vb[v] : 255; }
 };
 
 // K'[i] = sum of i's arc weights (self-loop once); Sigma'[i] = K'[i].
@@ -318,7 +318,7 @@ __device__ __forceinline__ bool apply_async(const MoveArgs& a, int32_t i, int32_
 // and count i among their moved neighbours (learned-pruner features).
 __device__ __forceinline__ void mark_one(const MoveArgs& a, int32_t i, int32_t j) {
     if (j == i) return;
-    if (a.prune && a.mark[j] != a.stamp_next) a.mark[j] = a.stamp_next;
+    if (a.prune) a.fnext[j] = 1;
     if (a.learn) atomicAdd(&a.f_nm[j], 1);
 }
 template <int G, typename OffT, int WK>
@@ -501,10 +501,11 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
 // one workgroup each, accumulate K_{i->d} in an LDS table and add it into the
 // hub's global table; (2) one workgroup per hub scans its table, decides and
 // (ASYNC) applies the move, then clears the table; (3) chunks of the movers'
-// rows stamp their neighbours.  Queued hubs: all in the first iteration of a
-// pass (or without pruning), else those stamped by the previous iteration.
+// rows flag their neighbours.  Queued hubs: all in a sweep (the first
+// iteration of a pass, or without pruning), else those flagged by the
+// previous iteration.
 __device__ __forceinline__ bool hub_queued(const MoveArgs& a, int32_t v) {
-    return a.all_queued || a.mark[v] == a.stamp_cur;
+    return a.all_queued || a.fcur[v];
 }
 // largest h in [0, n) with pre[h] - base <= x
 __device__ __forceinline__ int32_t owner_of(const int64_t* pre, int32_t n, int64_t base, int64_t x) {
@@ -619,8 +620,8 @@ __global__ void __launch_bounds__(1024) k_hub_mark(MoveArgs a) {
 }
 
 // SYNC: apply the recorded decisions of the iteration's queue together, then
-// stamp the movers' neighbours for the next iteration (hubs' rows are
-// stamped by the chunked hub marking).  One wave per 64 queue entries: each
+// flag the movers' neighbours for the next iteration (hubs' rows are
+// flagged by the chunked hub marking).  One wave per 64 queue entries: each
 // lane applies its own vertex's move; the wave then walks each mover's row.
 template <typename OffT>
 __global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a, const int32_t* __restrict__ list, int64_t count) {
@@ -661,7 +662,7 @@ void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int
         k_classify<int32_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, B, vbucket, Cp, K, Sig);
 }
 
-void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint32_t* mark, uint32_t stamp, int use_mark,
+void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags,
                         int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
                         hipStream_t s) {
     constexpr int NB = NB_MOVE + 1;
@@ -670,8 +671,8 @@ void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint32_t* mark,
         hipMemsetAsync(totals, 0, NB * sizeof(int32_t), s);
         return;
     }
-    if (use_mark) {
-        MarkBucket bf{vbucket, mark, stamp};
+    if (use_flags) {
+        MarkBucket bf{vbucket, flags};
         k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb);
         scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
         k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out);
