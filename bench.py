@@ -111,7 +111,7 @@ def learned_leg(lv, torch, g, off, idx, w, mode, args, q_plain, dt_plain):
           f"{t_train:.1f}s", file=sys.stderr, flush=True)
     extra = {} if args.async_coherent is None else {"async_coherent": args.async_coherent}
     L = lv.Louvain(off, idx, w, mode=mode, pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
-                   pruner_threshold=args.threshold, **extra)
+                   pruner_threshold=args.threshold, guard_tolerance=1 if args.guard == "tolerance" else 0, **extra)
     dt, q, st = timed_runs(L, args.steps, args.warmup)
     L.close()
     print(f"[bench] learned: {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), sweeps={st.sweeps} "
@@ -119,7 +119,7 @@ def learned_leg(lv, torch, g, off, idx, w, mode, args, q_plain, dt_plain):
     return {"value": round(g.nnz / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
             "speedup_vs_plain": round(dt_plain / dt, 3), "modularity": round(q, 6),
             "dq_vs_plain": round(q - q_plain, 6), "equal_modularity": abs(q - q_plain) <= 0.002,
-            "threshold": args.threshold, "guard": "tolerance", "passes": st.passes, "iterations": st.iterations,
+            "threshold": args.threshold, "guard": args.guard, "passes": st.passes, "iterations": st.iterations,
             "sweeps": st.sweeps, "pruned": st.pruned, "vertices_evaluated": st.vertices_evaluated,
             "arcs_scanned": st.arcs_scanned,
             "training": {"graphs": "R-MAT scale 18, edge factor 16, seeds 1018-1020", "samples": int(S.shape[0]),
@@ -139,6 +139,9 @@ def main():
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-pruner leg")
     ap.add_argument("--threshold", type=float, default=0.5, help="learned pruner: keep iff sigmoid >= threshold")
+    ap.add_argument("--guard", default="strict", choices=["strict", "tolerance"],
+                    help="learned pruner: a pass ends at a full sweep with no positive-gain move (strict) "
+                         "or whose gain sum passes the tolerance test")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration run) and exit")
     ap.add_argument("--async-coherent", type=int, default=None, choices=[0, 1],

@@ -140,7 +140,8 @@ typedef struct {
     /* ASYNC only: apply async_slices to the first this-many iterations of
      * every pass (0 = to every iteration). */
     int32_t async_slice_iters;
-    /* LEARNED pruner only: exit test of a sweep (0 strict, 1 tolerance). */
+    /* LEARNED pruner only: exit test of a sweep (0 strict, the default: no
+     * positive-gain move left; 1 tolerance). */
     int32_t guard_tolerance;
     /* ASYNC only: at least this many queued vertices per slice (default 32);
      * an iteration uses min(async_slices, queued / async_slice_min) slices. */

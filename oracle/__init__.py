@@ -129,7 +129,7 @@ class Params:
     mode: int = ASYNC
     pick_less: int = 4
     prune: int = 1
-    guard_tolerance: int = 1          # PRUNE_LEARNED: sweep exit test (0 strict, 1 tolerance)
+    guard_tolerance: int = 0          # PRUNE_LEARNED: sweep exit test (0 strict, 1 tolerance)
     mlp: np.ndarray | None = None     # PRUNE_LEARNED: MLP_PARAMS float32 weights
     threshold: float = 0.5            # PRUNE_LEARNED: evaluate iff sigmoid(logit) >= threshold
     sample_per_mille: int = 0         # training-sample selection rate

@@ -306,7 +306,7 @@ void louvain_params_default(louvain_params* p) {
     p->bucket_order = 0;
     p->async_slices = 64;
     p->async_slice_iters = 0;
-    p->guard_tolerance = 1;
+    p->guard_tolerance = 0;
     p->async_slice_min = 32;
     p->async_hub_groups = 16;
     p->async_min_label = 1;

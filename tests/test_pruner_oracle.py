@@ -273,7 +273,8 @@ def test_drop_all_equals_no_pruning(mode):
     with the tolerance exit this is exactly the unpruned method."""
     g = gg.rmat(9, 8, seed=2, wmax=3)
     w8 = rand_weights(4)
-    a = oracle.louvain(g, oracle.Params(mode=mode, prune=oracle.PRUNE_LEARNED, mlp=w8, threshold=1.0), trace=True)
+    a = oracle.louvain(g, oracle.Params(mode=mode, prune=oracle.PRUNE_LEARNED, mlp=w8, threshold=1.0,
+                                        guard_tolerance=1), trace=True)
     b = oracle.louvain(g, oracle.Params(mode=mode, prune=oracle.PRUNE_NONE), trace=True)
     assert np.array_equal(a.membership, b.membership)
     assert len(a.iters) == len(b.iters) and a.sweeps == len(a.iters)
