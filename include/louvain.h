@@ -157,6 +157,12 @@ typedef struct {
     int32_t async_min_label;
     const float* pruner_weights; /* LEARNED: device, LOUVAIN_MLP_PARAMS floats, read during louvain_run */
     double pruner_threshold;     /* LEARNED: theta */
+    /* ASYNC only: 1 = slice s takes every slices-th entry of each bucket's
+     * id-sorted queue starting at entry s (each slice samples every part of
+     * the id range; in a batch, every graph); 0 = slice s takes the s-th
+     * contiguous share (default; closer to the sequential order). */
+    int32_t async_interleave;
+    int32_t reserved2;
 } louvain_params;
 
 /* Per-run counters, filled by louvain_get_stats after louvain_run. */
@@ -246,6 +252,31 @@ louvain_status louvain_get_kernel_stats(louvain_t* h, louvain_kernel_stat* out, 
 /* Install trace callbacks (either may be NULL).  Tracing copies state to the
  * host after every iteration and pass; it is for testing, not speed. */
 louvain_status louvain_set_trace(louvain_t* h, louvain_iter_fn iter_fn, louvain_pass_fn pass_fn, void* user);
+
+/* Batched runs (many independent graphs in one run).  g is the union of
+ * `count` graphs laid end to end in one CSR: graph k owns the vertices
+ * [vbase[k], vbase[k+1]) (vbase: host array of count+1 entries, vbase[0] = 0,
+ * non-decreasing, vbase[count] = n) and every arc of a vertex must stay in its
+ * graph (checked in create; LOUVAIN_ERR_INVALID otherwise).  Every graph goes
+ * through the method of louvain_run on its own -- its own total weight W_k,
+ * tolerance test, iteration count, shrink tests and pass count -- as if run
+ * alone; the graphs share every kernel launch.  Pruner NONE and FLAGS only.
+ * louvain_get_membership writes, for each vertex, its community within its
+ * graph (0 .. communities_k - 1, ascending final label); louvain_modularity is
+ * refused on a batched handle.  louvain_workspace_size_batch: bytes for a
+ * batched handle (count = 0 gives the single-graph size). */
+louvain_status louvain_workspace_size_batch(const louvain_graph* g, int64_t count, const louvain_params* p,
+                                            size_t* bytes);
+louvain_status louvain_create_batch(const louvain_graph* g, const int64_t* vbase, int64_t count,
+                                    const louvain_params* p, void* stream, void* workspace, size_t workspace_bytes,
+                                    louvain_t** out);
+/* Per-graph modularity of the last run (Eq. (1) on each graph with its own
+ * W_k): host arrays q[count], num[2*count], den[2*count] (each exact value
+ * as a (hi, lo) int64 pair, den = W_k^2; W_k = 0 gives 0/1).  Any may be NULL. */
+louvain_status louvain_modularity_batch(louvain_t* h, double* q, int64_t* num, int64_t* den);
+/* Per-graph passes, local-moving iterations and final community counts of
+ * the last run (host arrays of count entries; any may be NULL). */
+louvain_status louvain_batch_results(louvain_t* h, int32_t* passes, int32_t* iterations, int64_t* communities);
 
 /* Record pruner training samples during later runs of h (any mode and
  * pruner): in every iteration t >= 1 that is not a sweep, each vertex v of the

@@ -33,7 +33,9 @@ EXPORTED = ["louvain_params_default", "louvain_workspace_size", "louvain_create"
             "louvain_get_membership", "louvain_modularity", "louvain_get_stats", "louvain_set_profiling",
             "louvain_get_kernel_stats", "louvain_set_trace", "louvain_last_error", "louvain_destroy",
             "louvain_collect_samples", "louvain_sample_count", "louvain_pruner_init", "louvain_pruner_predict",
-            "louvain_pruner_loss_grad", "louvain_pruner_scratch_floats", "louvain_pruner_train"]
+            "louvain_pruner_loss_grad", "louvain_pruner_scratch_floats", "louvain_pruner_train",
+            "louvain_workspace_size_batch", "louvain_create_batch", "louvain_modularity_batch",
+            "louvain_batch_results"]
 
 
 class LouvainGraph(ctypes.Structure):
@@ -51,7 +53,8 @@ class LouvainParams(ctypes.Structure):
                 ("async_slices", ctypes.c_int32), ("async_slice_iters", ctypes.c_int32),
                 ("guard_tolerance", ctypes.c_int32), ("async_slice_min", ctypes.c_int32),
                 ("async_hub_groups", ctypes.c_int32), ("async_min_label", ctypes.c_int32),
-                ("pruner_weights", ctypes.c_void_p), ("pruner_threshold", ctypes.c_double)]
+                ("pruner_weights", ctypes.c_void_p), ("pruner_threshold", ctypes.c_double),
+                ("async_interleave", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class LouvainStats(ctypes.Structure):
@@ -113,6 +116,16 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_last_error.argtypes = [vp]
     lib.louvain_destroy.restype = None
     lib.louvain_destroy.argtypes = [vp]
+    lib.louvain_workspace_size_batch.restype = ctypes.c_int
+    lib.louvain_workspace_size_batch.argtypes = [ctypes.POINTER(LouvainGraph), ctypes.c_int64,
+                                                 ctypes.POINTER(LouvainParams), ctypes.POINTER(ctypes.c_size_t)]
+    lib.louvain_create_batch.restype = ctypes.c_int
+    lib.louvain_create_batch.argtypes = [ctypes.POINTER(LouvainGraph), _I64P, ctypes.c_int64,
+                                         ctypes.POINTER(LouvainParams), vp, vp, sz, ctypes.POINTER(vp)]
+    lib.louvain_modularity_batch.restype = ctypes.c_int
+    lib.louvain_modularity_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_double), _I64P, _I64P]
+    lib.louvain_batch_results.restype = ctypes.c_int
+    lib.louvain_batch_results.argtypes = [vp, _I32P, _I32P, _I64P]
     lib.louvain_collect_samples.restype = ctypes.c_int
     lib.louvain_collect_samples.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32]
     lib.louvain_sample_count.restype = ctypes.c_int
@@ -213,6 +226,42 @@ def louvain_last_error(h=None) -> str:
     return msg.decode() if msg else ""
 
 
+def louvain_workspace_size_batch(g: LouvainGraph, count: int, p: LouvainParams) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().louvain_workspace_size_batch(ctypes.byref(g), count, ctypes.byref(p), ctypes.byref(n)))
+    return int(n.value)
+
+
+def louvain_create_batch(g: LouvainGraph, vbase, p: LouvainParams, stream: int, workspace: int,
+                         workspace_bytes: int):
+    vb = (ctypes.c_int64 * len(vbase))(*[int(x) for x in vbase])
+    h = ctypes.c_void_p()
+    _check(load_library().louvain_create_batch(ctypes.byref(g), vb, len(vbase) - 1, ctypes.byref(p), stream,
+                                               workspace, workspace_bytes, ctypes.byref(h)))
+    return h
+
+
+def louvain_modularity_batch(h, count: int):
+    """Per-graph (q, numerator, denominator) lists; exact values as Python ints."""
+    q = (ctypes.c_double * count)()
+    num = (ctypes.c_int64 * (2 * count))()
+    den = (ctypes.c_int64 * (2 * count))()
+    _check(load_library().louvain_modularity_batch(h, q, num, den), h)
+
+    def i128(a, k):
+        return (int(a[2 * k]) << 64) + (int(a[2 * k + 1]) & ((1 << 64) - 1))
+    return list(q), [i128(num, k) for k in range(count)], [i128(den, k) for k in range(count)]
+
+
+def louvain_batch_results(h, count: int):
+    """Per-graph (passes, iterations, communities) lists."""
+    pa = (ctypes.c_int32 * count)()
+    it = (ctypes.c_int32 * count)()
+    co = (ctypes.c_int64 * count)()
+    _check(load_library().louvain_batch_results(h, pa, it, co), h)
+    return list(pa), list(it), list(co)
+
+
 def louvain_collect_samples(h, buffer_ptr: int, capacity: int, sample_per_mille: int) -> None:
     _check(load_library().louvain_collect_samples(h, buffer_ptr or None, capacity, sample_per_mille), h)
 
@@ -266,7 +315,8 @@ class Louvain:
     The workspace is a torch uint8 tensor; kernels run on the current stream.
     """
 
-    def __init__(self, offsets, indices, weights=None, params: LouvainParams | None = None, **overrides):
+    def __init__(self, offsets, indices, weights=None, params: LouvainParams | None = None, vbase=None,
+                 **overrides):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU available: the Louvain library runs only on the GPU")
@@ -295,10 +345,15 @@ class Louvain:
         g.weights = weights.data_ptr() if weights is not None else None
         self.graph = g
         self.n = n
-        nbytes = louvain_workspace_size(g, self.params)
+        self.count = 0 if vbase is None else len(vbase) - 1
+        nbytes = louvain_workspace_size_batch(g, self.count, self.params)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=offsets.device)
         self.stream = torch.cuda.current_stream(offsets.device)
-        self.h = louvain_create(g, self.params, self.stream.cuda_stream, self.workspace.data_ptr(), nbytes)
+        if vbase is None:
+            self.h = louvain_create(g, self.params, self.stream.cuda_stream, self.workspace.data_ptr(), nbytes)
+        else:
+            self.h = louvain_create_batch(g, vbase, self.params, self.stream.cuda_stream, self.workspace.data_ptr(),
+                                          nbytes)
         self._cb = None
 
     def run(self):
@@ -314,6 +369,14 @@ class Louvain:
 
     def modularity(self):
         return louvain_modularity(self.h)
+
+    def modularity_batch(self):
+        """Per-graph (q, numerator, denominator) lists of a batched handle."""
+        return louvain_modularity_batch(self.h, self.count)
+
+    def batch_results(self):
+        """Per-graph (passes, iterations, communities) lists of a batched handle."""
+        return louvain_batch_results(self.h, self.count)
 
     def stats(self) -> LouvainStats:
         return louvain_get_stats(self.h)
@@ -369,6 +432,31 @@ class Louvain:
             self.close()
         except Exception:
             pass
+
+
+def batch_tensors(graphs, device="cuda", unit_weights: bool | None = None):
+    """Lay graphgen.CSRGraphs end to end: returns (offsets, indices, weights-or-None,
+    vbase) for Louvain(..., vbase=vbase).  Offsets are int64 when the union has
+    2^31 or more arcs."""
+    import numpy as np
+    import torch
+    ns = [g.n for g in graphs]
+    ms = [int(g.offsets[-1]) for g in graphs]
+    vbase = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    ebase = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+    big = ebase[-1] > 0x7fffffff
+    off = np.empty(vbase[-1] + 1, dtype=np.int64)
+    off[-1] = ebase[-1]
+    idx = np.empty(ebase[-1], dtype=np.int32)
+    wts = np.empty(ebase[-1], dtype=np.int32)
+    for k, g in enumerate(graphs):
+        off[vbase[k]:vbase[k + 1]] = np.asarray(g.offsets[:-1], dtype=np.int64) + ebase[k]
+        idx[ebase[k]:ebase[k + 1]] = np.asarray(g.indices, dtype=np.int64) + vbase[k]
+        wts[ebase[k]:ebase[k + 1]] = g.weights
+    unit = bool(unit_weights) if unit_weights is not None else bool(wts.size == 0 or wts.max() == 1)
+    o = torch.from_numpy(off if big else off.astype(np.int32)).to(device)
+    w = None if unit else torch.from_numpy(wts).to(device)
+    return o, torch.from_numpy(idx).to(device), w, vbase.tolist()
 
 
 def graph_tensors(g, device="cuda", offset_bits: int = 32, unit_weights: bool | None = None):

@@ -739,6 +739,19 @@ void launch_rowlen_to_offsets(const int32_t* rowlen, int64_t ncom, void* goff, i
     else scan_i32_to_i32(rowlen, (int32_t*)goff, ncom, scratch, s);
 }
 
+void launch_modularity_arcs(const LevelView& L0, const int32_t* C, i64* sigin, i64* sigtot, hipStream_t s) {
+    if (L0.n <= 0) return;
+    LevelTypes t = L0.t;
+    t.acc64 = 0;
+    dispatch_types(t, [&](auto o, auto w, auto) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        Graph<OffT, WK> g{(const OffT*)L0.off, L0.idx, L0.w};
+        const unsigned grid = (unsigned)std::min<int64_t>(16384, (L0.n + 3) / 4);
+        k_mod_arcs<OffT, WK><<<grid, 256, 0, s>>>(g, L0.n, C, sigin, sigtot);
+    });
+}
+
 void launch_modularity(const LevelView& L0, const int32_t* C, int64_t ncom, i64 W, i64* sigin, i64* sigtot,
                        Ctl* ctl, hipStream_t s) {
     if (L0.n <= 0) return;

@@ -46,12 +46,14 @@ struct Layout {
     size_t hidx, hw, sup_off[2], sup_idx[2], sup_w[2], pool_keys, pool_vals, scan;
     size_t md, mpos, bnch, bchpre, bitmaps, gdec, blkcnt, blkoff;
     size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots;
+    // batched runs (count graphs; absent for a single graph)
+    size_t gid[2], gid0, Wg, gact, Sg, gcnt, cmin, vbase, gq, segcnt, segstart, prefall;
     int64_t bitmap_words;
     int64_t pool_entries;
     size_t total;
 };
 
-bool make_layout(int64_t n, int64_t m, Layout* L) {
+bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes > 0 ? bytes : 1); return at; };
     const size_t N = (size_t)n, M = (size_t)m;
@@ -95,7 +97,24 @@ bool make_layout(int64_t n, int64_t m, Layout* L) {
     L->pool_vals = take((size_t)pool * 8);
     L->hslots = take((size_t)pool / 2 * 4);
     L->hcnt = take((N + 1) * 4);
-    L->scan = take(scan_scratch_bytes(n + 2));
+    if (count > 0) {
+        const size_t G = (size_t)count;
+        L->gid[0] = take(N * 4);
+        L->gid[1] = take(N * 4);
+        L->gid0 = take(N * 4);
+        L->Wg = take(G * 8);
+        L->gact = take(G);
+        L->Sg = take(G * 16);
+        L->gcnt = take(G * 16);   // per graph: vertices with arcs, used communities
+        L->cmin = take(G * 4);
+        L->vbase = take((G + 1) * 8);
+        L->gq = take(G * 16);     // per-graph modularity numerators
+        const size_t S = (size_t)std::max(1, slices);
+        L->segcnt = take((size_t)NB_MOVE * G * 4);
+        L->segstart = take((size_t)NB_MOVE * (G + 1) * 4);
+        L->prefall = take((size_t)NB_MOVE * S * (G + 1) * 4);
+    }
+    L->scan = take(scan_scratch_bytes(std::max(n, count) + 2));
     L->gdec = take(N * 4);
     L->blkcnt = take((size_t)(MAX_BUCKETS * (bucket_blocks(n + 1) + 1) + 8) * 4);
     L->blkoff = take((size_t)(MAX_BUCKETS * (bucket_blocks(n + 1) + 1) + 8) * 4);
@@ -142,6 +161,14 @@ struct louvain_s {
     int sup_off64 = 0, sup_wk = 1;
     bool ran = false;
     int64_t ncom = 0;
+    // batched runs: number of graphs (0 = a single graph), vertex bases, and
+    // per-graph results of the last run
+    int64_t nb = 0;
+    std::vector<int64_t> vbase;
+    std::vector<u64> Wg;
+    std::vector<int32_t> b_passes, b_iters;
+    std::vector<int64_t> b_comms;
+    std::vector<int32_t> b_cbase;  // first final community id of every graph (union numbering)
     louvain_stats st{};
     std::string err = "no error";
     void* pinned = nullptr;  // readback staging
@@ -203,9 +230,9 @@ void timed(louvain_t* h, int kind, int64_t bytes, Fn&& fn) {
     if (!h->prof) { fn(); return; }
     hipEvent_t a = next_event(h), b = next_event(h);
     if (!a || !b) { fn(); return; }
-    hipEventRecord(a, h->stream);
+    (void)hipEventRecord(a, h->stream);
     fn();
-    hipEventRecord(b, h->stream);
+    (void)hipEventRecord(b, h->stream);
     h->recs.push_back({kind, a, b, bytes});
 }
 
@@ -310,22 +337,33 @@ void louvain_params_default(louvain_params* p) {
     p->async_slice_min = 32;
     p->async_hub_groups = 16;
     p->async_min_label = 1;
+    p->async_interleave = 0;
     p->pruner_weights = nullptr;
     p->pruner_threshold = 0.5;
 }
 
 louvain_status louvain_workspace_size(const louvain_graph* g, const louvain_params* p, size_t* bytes) {
+    return louvain_workspace_size_batch(g, 0, p, bytes);
+}
+
+louvain_status louvain_workspace_size_batch(const louvain_graph* g, int64_t count, const louvain_params* p,
+                                            size_t* bytes) {
     if (!g || !p || !bytes) return fail(nullptr, LOUVAIN_ERR_INVALID, "null argument");
     if (g->n < 0 || g->nnz < 0 || g->n > 0x7ffffffeLL)
         return fail(nullptr, LOUVAIN_ERR_INVALID, "n must be in [0, 2^31-2] and nnz >= 0");
+    if (count < 0 || count > 0x7ffffffeLL) return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid graph count");
     Layout L;
-    make_layout(g->n, g->nnz, &L);
+    make_layout(g->n, g->nnz, count, p->async_slices, &L);
     *bytes = L.total;
     return LOUVAIN_OK;
 }
 
-louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, void* stream, void* workspace,
-                              size_t workspace_bytes, louvain_t** out) {
+}  // extern "C"
+
+namespace {
+
+louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t count, const louvain_params* p,
+                           void* stream, void* workspace, size_t workspace_bytes, louvain_t** out) {
     if (!out) return fail(nullptr, LOUVAIN_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!g || !p) return fail(nullptr, LOUVAIN_ERR_INVALID, "null graph or params");
@@ -348,8 +386,17 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
         return fail(nullptr, LOUVAIN_ERR_INVALID, "the learned pruner needs pruner_weights");
     if (p->pruner_threshold != p->pruner_threshold)
         return fail(nullptr, LOUVAIN_ERR_INVALID, "pruner_threshold is NaN");
+    if (count > 0) {
+        if (!vbase) return fail(nullptr, LOUVAIN_ERR_INVALID, "vbase is NULL");
+        if (vbase[0] != 0 || vbase[count] != g->n)
+            return fail(nullptr, LOUVAIN_ERR_INVALID, "vbase must start at 0 and end at n");
+        for (int64_t k = 0; k < count; k++)
+            if (vbase[k + 1] < vbase[k]) return fail(nullptr, LOUVAIN_ERR_INVALID, "vbase must be non-decreasing");
+        if (p->pruner == LOUVAIN_PRUNE_LEARNED)
+            return fail(nullptr, LOUVAIN_ERR_INVALID, "batched runs support pruner NONE and FLAGS");
+    }
     Layout lay;
-    make_layout(g->n, g->nnz, &lay);
+    make_layout(g->n, g->nnz, count, p->async_slices, &lay);
     if (!workspace || workspace_bytes < lay.total || ((uintptr_t)workspace % ALIGN) != 0)
         return fail(nullptr, LOUVAIN_ERR_WORKSPACE, "workspace must be %zu bytes, 256-byte aligned (got %zu)",
                     lay.total, workspace_bytes);
@@ -362,6 +409,8 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
     h->ws = (char*)workspace;
     h->ws_bytes = workspace_bytes;
     h->lay = lay;
+    h->nb = count;
+    if (count > 0) h->vbase.assign(vbase, vbase + count + 1);
     h->L0.n = g->n;
     h->L0.nnz = g->nnz;
     h->L0.off = g->offsets;
@@ -382,7 +431,7 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
         h->err = "pinned host allocation failed";
         return bail(LOUVAIN_ERR_HIP);
     }
-    // zero control block, pruning stamps and moved-iteration tags
+    // zero control block, pruning flags and moved-iteration tags
     if (hipMemsetAsync(h->ctl(), 0, sizeof(Ctl), h->stream) != hipSuccess ||
         hipMemsetAsync(h->at<uint8_t>(lay.mark), 0, (size_t)std::max<int64_t>(g->n, 1) * 2, h->stream) !=
             hipSuccess ||
@@ -424,10 +473,49 @@ louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, v
         h->err = "total weight exceeds 2^62";
         return bail(LOUVAIN_ERR_OVERFLOW);
     }
+    u64 wmax = c.wsum;
+    if (count > 0) {
+        // graph ids, per-graph total weights, arcs confined to their graph
+        int64_t* vb_dev = h->at<int64_t>(lay.vbase);
+        u64* Wg_dev = h->at<u64>(lay.Wg);
+        if (hipMemcpyAsync(vb_dev, vbase, (size_t)(count + 1) * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipMemsetAsync(Wg_dev, 0, (size_t)count * 8, h->stream) != hipSuccess) {
+            h->err = "batch initialisation failed";
+            return bail(LOUVAIN_ERR_HIP);
+        }
+        launch_gid_init(vb_dev, count, g->n, h->at<int32_t>(lay.gid0), h->stream);
+        launch_graph_weights(h->L0, h->at<int32_t>(lay.gid0), Wg_dev, h->ctl(), h->stream);
+        h->Wg.resize(count);
+        if (readback(h, h->Wg.data(), Wg_dev, (size_t)count * 8) != LOUVAIN_OK ||
+            readback(h, &c, h->ctl(), sizeof(Ctl)) != LOUVAIN_OK)
+            return bail(LOUVAIN_ERR_HIP);
+        if (c.err & 8) {
+            h->err = "invalid batch: an arc joins two different graphs";
+            return bail(LOUVAIN_ERR_INVALID);
+        }
+        wmax = 0;
+        for (u64 x : h->Wg) wmax = std::max(wmax, x);
+    }
     h->sup_off64 = g->nnz > 0x7fffffffLL;
-    h->sup_wk = h->W < 0x7fffffffLL ? 1 : 2;
+    h->sup_wk = wmax < 0x7fffffffULL ? 1 : 2;
     *out = h;
     return LOUVAIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+louvain_status louvain_create(const louvain_graph* g, const louvain_params* p, void* stream, void* workspace,
+                              size_t workspace_bytes, louvain_t** out) {
+    return create_impl(g, nullptr, 0, p, stream, workspace, workspace_bytes, out);
+}
+
+louvain_status louvain_create_batch(const louvain_graph* g, const int64_t* vbase, int64_t count,
+                                    const louvain_params* p, void* stream, void* workspace, size_t workspace_bytes,
+                                    louvain_t** out) {
+    if (count < 1) return fail(nullptr, LOUVAIN_ERR_INVALID, "count must be >= 1");
+    return create_impl(g, vbase, count, p, stream, workspace, workspace_bytes, out);
 }
 
 }  // extern "C"
@@ -517,16 +605,61 @@ louvain_status Runner::run() {
     std::vector<int32_t> hcp;
     std::vector<int64_t> hsig;
 
+    // batched runs: per-graph state (the graphs move in lockstep passes; a
+    // graph converged in the current pass, or stopped, is skipped)
+    const int64_t nbg = H->nb;
+    const bool batch = nbg > 0;
+    int32_t* gidb[2] = {batch ? at<int32_t>(Y.gid[0]) : nullptr, batch ? at<int32_t>(Y.gid[1]) : nullptr};
+    int gsel = 0;
+    uint8_t* gact_dev = batch ? at<uint8_t>(Y.gact) : nullptr;
+    u64* Wg_dev = batch ? at<u64>(Y.Wg) : nullptr;
+    u64* Sg_dev = batch ? at<u64>(Y.Sg) : nullptr;
+    u64* gcnt_dev = batch ? at<u64>(Y.gcnt) : nullptr;
+    std::vector<uint8_t> alive(nbg, 1), act(nbg, 0), ran(nbg, 0);
+    std::vector<int32_t> li_g(nbg, 0);
+    std::vector<int64_t> nver(nbg, 0);
+    std::vector<u64> hS(2 * nbg), hcnt(2 * nbg);
+    u64 Wmax = (u64)W;
+    if (batch) {
+        for (int64_t g = 0; g < nbg; g++) nver[g] = H->vbase[g + 1] - H->vbase[g];
+        H->b_passes.assign(nbg, 0);
+        H->b_iters.assign(nbg, 0);
+        H->b_comms.assign(nbg, 0);
+        Wmax = 0;
+        for (u64 x : H->Wg) Wmax = std::max(Wmax, x);
+        if (n0 > 0) HIPCHK(H, hipMemcpyAsync(gidb[0], at<int32_t>(Y.gid0), (size_t)n0 * 4, hipMemcpyDeviceToDevice, s));
+    }
+    auto upload_act = [&]() -> louvain_status {
+        if (nbg <= (1 << 16)) {
+            memcpy(H->pinned_up, act.data(), (size_t)nbg);
+            HIPCHK(H, hipMemcpyAsync(gact_dev, H->pinned_up, (size_t)nbg, hipMemcpyHostToDevice, s));
+        } else {
+            HIPCHK(H, hipMemcpyAsync(gact_dev, act.data(), (size_t)nbg, hipMemcpyHostToDevice, s));
+            HIPCHK(H, hipStreamSynchronize(s));
+        }
+        return LOUVAIN_OK;
+    };
+
     for (int pass = 0; P.max_passes <= 0 || pass < P.max_passes; pass++) {
         const int64_t n = L.n;
         have_newid = false;
+        const int32_t* gid = batch ? gidb[gsel] : nullptr;
+        if (batch) {
+            for (int64_t g = 0; g < nbg; g++) {
+                act[g] = ran[g] = alive[g];
+                li_g[g] = P.max_iterations;
+            }
+            if ((st = upload_act()) != LOUVAIN_OK) return st;
+            HIPCHK(H, hipMemsetAsync(gcnt_dev, 0, (size_t)nbg * 16, s));
+            launch_nonisolated_by_graph(L, gid, gcnt_dev, s);
+        }
         // ---------------- pass init: classify, bucket lists, K', Sigma'
         HIPCHK(H, hipMemsetAsync(&ctl()->kmax, 0, sizeof(u64), s));
         const int NBT = NB_MOVE + 1;  // LDS buckets + hub
         int32_t bcount[MAX_BUCKETS] = {};
         timed(H, K_PASS_INIT, 0, [&] {
             launch_classify(L, H->mb, vb, Cp, K, Sig, s);
-            bucketize_vertices(n, vb, nullptr, 0, blkcnt, blkoff, blist, ctl()->bcount, scan, s);
+            bucketize_vertices(n, vb, nullptr, 0, nullptr, nullptr, blkcnt, blkoff, blist, ctl()->bcount, scan, s);
         });
         if ((st = readback(H, bcount, ctl()->bcount, NBT * sizeof(int32_t))) != LOUVAIN_OK) return st;
         int64_t segs[MAX_BUCKETS + 1];
@@ -561,7 +694,7 @@ louvain_status Runner::run() {
         }
         u64 kmax = 0;
         if ((st = readback(H, &kmax, &ctl()->kmax, sizeof(u64))) != LOUVAIN_OK) return st;
-        const bool wide = (unsigned __int128)(u64)W * kmax >= ((unsigned __int128)1 << 62);
+        const bool wide = (unsigned __int128)Wmax * kmax >= ((unsigned __int128)1 << 62);
         LevelView LM = L;
         LM.t.acc64 = kmax >= ((u64)1 << 32);
 
@@ -581,6 +714,7 @@ louvain_status Runner::run() {
             const int pl = P.pick_less > 0 && ((t + P.pick_less / 2) % P.pick_less) == 0;
             HIPCHK(H, hipMemsetAsync(ctl(), 0, CTL_ITER_BYTES, s));
             if (learn) HIPCHK(H, hipMemsetAsync(f_nm, 0, (size_t)n * 4, s));
+            if (batch) HIPCHK(H, hipMemsetAsync(Sg_dev, 0, (size_t)nbg * 16, s));
             const uint32_t stamp_next = ++H->stamp;  // unique tag of this iteration
             uint8_t* fnext = flags + (size_t)(stamp_next & 1) * (size_t)n0;
             const uint8_t* fcur = flags + (size_t)((stamp_next + 1) & 1) * (size_t)n0;
@@ -613,6 +747,10 @@ louvain_status Runner::run() {
             a.hub_vals = at<void>(Y.pool_vals);
             a.hub_cnt = at<int32_t>(Y.hcnt);
             a.hub_slots = at<int32_t>(Y.hslots);
+            a.gid = gid;
+            a.Wg = Wg_dev;
+            a.gact = gact_dev;
+            a.Sg = Sg_dev;
             a.learn = learn;
             a.itag = stamp_next;
             a.f_own = f_own;
@@ -649,9 +787,51 @@ louvain_status Runner::run() {
             // hub groups: group k covers the static hub positions [k*nhub/hg, (k+1)*nhub/hg)
             // and runs with slice due(k) = (k+1)*ns/hg - 1
             const int hg = (!sync && P.async_hub_groups > 0) ? std::min(P.async_hub_groups, ns) : ns;
+            // batched ASYNC: slice sl takes the sl-th share of every graph's part
+            // of each bucket's queue (graphs are contiguous id ranges, so plain
+            // contiguous slices would hold whole graphs)
+            const bool segmented = batch && !sync && ns > 1;
+            int32_t* segcnt = segmented ? at<int32_t>(Y.segcnt) : nullptr;
+            int32_t* segstart = segmented ? at<int32_t>(Y.segstart) : nullptr;
+            int32_t* prefall = segmented ? at<int32_t>(Y.prefall) : nullptr;
+            std::vector<int32_t> segtot;
+            if (segmented) {
+                HIPCHK(H, hipMemsetAsync(segcnt, 0, (size_t)NB_MOVE * nbg * 4, s));
+                for (int b = 0; b < NB_MOVE; b++)
+                    launch_seg_count(cur_list + csegs[b], counts[b], gid, segcnt + (int64_t)b * nbg, s);
+                for (int b = 0; b < NB_MOVE; b++)
+                    scan_i32_to_i32(segcnt + (int64_t)b * nbg, segstart + (int64_t)b * (nbg + 1), nbg, scan, s);
+                launch_slice_prefix(segcnt, NB_MOVE, nbg, ns, prefall, s);
+                std::vector<int32_t> hseg((size_t)NB_MOVE * nbg);
+                if ((st = readback(H, hseg.data(), segcnt, hseg.size() * 4)) != LOUVAIN_OK) return st;
+                segtot.assign((size_t)NB_MOVE * ns, 0);
+                for (int b = 0; b < NB_MOVE; b++)
+                    for (int64_t g = 0; g < nbg; g++) {
+                        const int64_t len = hseg[(size_t)b * nbg + g];
+                        if (!len) continue;
+                        for (int k = 0; k < ns; k++)
+                            segtot[(size_t)b * ns + k] += (int32_t)(len * (k + 1) / ns - len * k / ns);
+                    }
+                a.seg_n = (int32_t)nbg;
+                a.seg_ns = ns;
+            }
             for (int sl = 0; sl < ns; sl++) {
-                auto lo_of = [&](int b) { return (int32_t)((int64_t)counts[b] * sl / ns); };
-                auto hi_of = [&](int b) { return (int32_t)((int64_t)counts[b] * (sl + 1) / ns); };
+                // entries of bucket b in this slice: contiguous share [lo, hi), or
+                // (interleaved) every ns-th entry from sl on
+                const bool inter = !sync && P.async_interleave && ns > 1;
+                auto lo_of = [&](int b) { return inter ? 0 : (int32_t)((int64_t)counts[b] * sl / ns); };
+                auto hi_of = [&](int b) {
+                    return inter ? (counts[b] > sl ? (counts[b] - sl + ns - 1) / ns : 0)
+                                 : (int32_t)((int64_t)counts[b] * (sl + 1) / ns);
+                };
+                a.lstride = inter ? ns : 1;
+                a.lphase = inter ? sl : 0;
+                a.seg_k = sl;
+                auto seg_rows = [&](int b, const int32_t** pre, const int32_t** st0, const int32_t** cnt) {
+                    *pre = prefall + ((int64_t)b * ns + sl) * (nbg + 1);
+                    *st0 = segstart + (int64_t)b * (nbg + 1);
+                    *cnt = segcnt + (int64_t)b * nbg;
+                };
                 int32_t h_lo = 0, h_hi = 0;  // hub positions due with this slice
                 for (int k = 0; k < hg; k++)
                     if ((int)(((int64_t)(k + 1) * ns) / hg) - 1 == sl) {
@@ -662,18 +842,23 @@ louvain_status Runner::run() {
                 FusedLists f{};
                 f.blk_pre[0] = 0;
                 for (int b = 0; b < 4; b++) {
-                    const int32_t lo = lo_of(b), hi = hi_of(b);
+                    const int32_t lo = segmented ? 0 : lo_of(b);
+                    const int32_t hi = segmented ? segtot[(size_t)b * ns + sl] : hi_of(b);
                     f.list[b] = cur_list + csegs[b] + lo;
                     f.count[b] = hi - lo;
+                    if (segmented) seg_rows(b, &f.seg_pre[b], &f.seg_start[b], &f.seg_cnt[b]);
                     const int ng = 256 / MOVE_G[b];
                     f.blk_pre[b + 1] = f.blk_pre[b] + (f.count[b] + ng - 1) / ng;
                 }
                 if (f.blk_pre[4] > 0) timed(H, K_MOVE_FUSED, 0, [&] { launch_move_fused(LM, mode, a, f, s); });
                 {
-                    const int32_t lo = lo_of(4), hi = hi_of(4);
+                    const int32_t lo = segmented ? 0 : lo_of(4);
+                    const int32_t hi = segmented ? segtot[(size_t)4 * ns + sl] : hi_of(4);
                     if (hi > lo) {
                         a.bucket = 4;
-                        timed(H, K_MOVE4, 0, [&] { launch_move(LM, 4, mode, a, cur_list + csegs[4] + lo, hi - lo, s); });
+                        MoveArgs a4 = a;
+                        if (segmented) seg_rows(4, &a4.seg_pre, &a4.seg_start, &a4.seg_cnt);
+                        timed(H, K_MOVE4, 0, [&] { launch_move(LM, 4, mode, a4, cur_list + csegs[4] + lo, hi - lo, s); });
                     }
                 }
                 if (!P.bucket_order && hubs_now && h_hi > h_lo) hubs_range(h_lo, h_hi, true, !sync);
@@ -685,12 +870,13 @@ louvain_status Runner::run() {
             if (learn) launch_learn_label(H->smp_buf, smp_lo, smp_hi, f_moved, stamp_next, s);
             if (prune && !learn)
                 timed(H, K_QUEUE, 0, [&] {
-                    bucketize_vertices(n, vb, fnext, 1, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
+                    bucketize_vertices(n, vb, fnext, 1, gid, gact_dev, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
                 });
             // read back the iteration's striped totals
             Ctl* hc = (Ctl*)H->pinned;
             HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
             if (H->prof) HIPCHK(H, hipMemcpyAsync(&hc->bstat, &ctl()->bstat, sizeof(hc->bstat), hipMemcpyDeviceToHost, s));
+            if (batch) HIPCHK(H, hipMemcpyAsync(hS.data(), Sg_dev, (size_t)nbg * 16, hipMemcpyDeviceToHost, s));
             HIPCHK(H, hipStreamSynchronize(s));
             IterTotals it = sum_iter(*hc);
             const unsigned __int128 S = it.S;
@@ -724,8 +910,28 @@ louvain_status Runner::run() {
                 H->itfn(H->user, pass, t, n, hcp.data(), hsig.data(), (int64_t)it.moves, (int64_t)(S >> 64),
                         (uint64_t)S);
             }
-            const bool conv = converged(S, W, P, pass);
-            if (!learn) {
+            // ASYNC: an iteration under Pick-Less rejects every move to a larger
+            // id, so its gain sum says nothing about convergence; only the
+            // other iterations may end the pass (SYNC keeps the exact rule)
+            const bool may_end = sync || !pl;
+            const bool conv = may_end && converged(S, W, P, pass);
+            if (batch) {
+                // per-graph tolerance tests; converged graphs stop moving for this pass
+                bool changed = false, any = false;
+                for (int64_t g = 0; g < nbg; g++) {
+                    if (!act[g]) continue;
+                    const unsigned __int128 Sg = ((unsigned __int128)hS[2 * g + 1] << 64) + hS[2 * g];
+                    if (may_end && converged(Sg, (int64_t)H->Wg[g], P, pass)) {
+                        li_g[g] = t + 1;
+                        act[g] = 0;
+                        changed = true;
+                    } else {
+                        any = true;
+                    }
+                }
+                if (!any) { li = t + 1; break; }
+                if (changed && (st = upload_act()) != LOUVAIN_OK) return st;
+            } else if (!learn) {
                 if (conv) { li = t + 1; break; }
             } else {
                 // LEARNED: only a sweep that passes the exit test ends the pass
@@ -758,7 +964,7 @@ louvain_status Runner::run() {
                     timed(H, K_LEARN_FILTER, 0, [&] { launch_learn_filter(fa, L.t.off64, s); });
                     if (prune)
                         timed(H, K_QUEUE, 0, [&] {
-                            bucketize_vertices(n, vb, fnext, 1, blkcnt, blkoff, qnext, ctl()->qcount,
+                            bucketize_vertices(n, vb, fnext, 1, gid, gact_dev, blkcnt, blkoff, qnext, ctl()->qcount,
                                                scan, s);
                         });
                     HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
@@ -824,6 +1030,8 @@ louvain_status Runner::run() {
                     H->st.iterations++;
                     if (H->itfn) H->itfn(H->user, pass, t + 1, n, hcp.data(), hsig.data(), 0, 0, 0);
                     li = t + 2;
+                    for (int64_t g = 0; g < nbg; g++)
+                        if (act[g]) li_g[g] = t + 2;
                     break;
                 }
             }
@@ -831,6 +1039,16 @@ louvain_status Runner::run() {
         H->st.passes++;
         if (pass < 32) H->st.iterations_per_pass[pass] = li;
         stopped_before_aggregate = true;
+        if (batch) {
+            li = 0;
+            for (int64_t g = 0; g < nbg; g++) {
+                if (!ran[g]) continue;
+                H->b_passes[g]++;
+                H->b_iters[g] += li_g[g];
+                li = std::max(li, li_g[g]);
+                if (li_g[g] <= 1) alive[g] = 0;  // globally converged
+            }
+        }
         if (li <= 1) break;
 
         // ---------------- community counts and shrink tests
@@ -840,18 +1058,40 @@ louvain_status Runner::run() {
         timed(H, K_AGG_PREP, 0, [&] {
             launch_mark_used(Cp, n, used, s);
             scan_i32_to_i32(used, newid, n, scan, s);
+            if (batch) launch_used_by_graph(used, n, gid, gcnt_dev + nbg, s);
         });
         int32_t gall = 0;
         if ((st = readback(H, &gall, newid + n, 4)) != LOUVAIN_OK) return st;
         have_newid = true;
         ncom_last = gall;
-        const int64_t isolated = n - nonisolated;
-        const int64_t gamma = gall - isolated, gamma_old = nonisolated;
         if (pass < 32) H->st.communities_per_pass[pass] = gall;
-        if (gamma == gamma_old) break;
-        if ((unsigned __int128)gamma * (unsigned __int128)P.agg_den >
-            (unsigned __int128)P.agg_num * (unsigned __int128)gamma_old)
-            break;
+        if (batch) {
+            // per-graph shrink tests (Gamma over vertices with arcs); every graph is
+            // aggregated while any graph continues (a stopped graph's aggregation
+            // is its final lookup, and it stays still afterwards)
+            if ((st = readback(H, hcnt.data(), gcnt_dev, (size_t)nbg * 16)) != LOUVAIN_OK) return st;
+            bool any = false;
+            for (int64_t g = 0; g < nbg; g++) {
+                const int64_t nonis = (int64_t)hcnt[g], usedg = (int64_t)hcnt[nbg + g];
+                if (ran[g] && alive[g]) {
+                    const int64_t gamma = usedg - (nver[g] - nonis), gamma_old = nonis;
+                    if (gamma == gamma_old ||
+                        (unsigned __int128)gamma * (unsigned __int128)P.agg_den >
+                            (unsigned __int128)P.agg_num * (unsigned __int128)gamma_old)
+                        alive[g] = 0;
+                }
+                any |= alive[g] != 0;
+                nver[g] = usedg;
+            }
+            if (!any) break;
+        } else {
+            const int64_t isolated = n - nonisolated;
+            const int64_t gamma = gall - isolated, gamma_old = nonisolated;
+            if (gamma == gamma_old) break;
+            if ((unsigned __int128)gamma * (unsigned __int128)P.agg_den >
+                (unsigned __int128)P.agg_num * (unsigned __int128)gamma_old)
+                break;
+        }
 
         // ---------------- renumber, dendrogram lookup, community CSR
         const int64_t ncom = gall;
@@ -865,6 +1105,7 @@ louvain_status Runner::run() {
         HIPCHK(H, hipMemsetAsync(cursor, 0, (ncom + 1) * 4, s));
         HIPCHK(H, hipMemsetAsync(cdeg, 0, (ncom + 1) * 8, s));
         int32_t* alist = at<int32_t>(Y.alist);
+        if (batch) launch_gid_next(used, newid, n, gid, gidb[gsel ^ 1], s);
         timed(H, K_AGG_PREP, 0, [&] {
             launch_relabel(Cp, n, newid, s);
             launch_dendrogram(C, n0, Cp, s);
@@ -978,6 +1219,7 @@ louvain_status Runner::run() {
         L.t.wk = H->sup_wk;
         L.t.acc64 = 0;
         cur_sup = nxt;
+        gsel ^= 1;
         stopped_before_aggregate = false;
         have_newid = false;
         if (H->pafn) {
@@ -1021,6 +1263,23 @@ louvain_status Runner::run() {
     } else {
         H->ncom = L.n;
     }
+    if (batch) {
+        // first final community id of every graph (union numbering), kept on
+        // the device for membership and modularity
+        int32_t* cmin = at<int32_t>(Y.cmin);
+        HIPCHK(H, hipMemsetAsync(cmin, 0x7f, (size_t)nbg * 4, s));
+        launch_graph_cmin(C, n0, at<int32_t>(Y.gid0), cmin, s);
+        H->b_cbase.resize(nbg + 1);
+        if ((st = readback(H, H->b_cbase.data(), cmin, (size_t)nbg * 4)) != LOUVAIN_OK) return st;
+        H->b_cbase[nbg] = (int32_t)H->ncom;
+        for (int64_t g = nbg - 1; g >= 0; g--)  // graphs without vertices: empty range
+            if (H->vbase[g + 1] == H->vbase[g]) H->b_cbase[g] = H->b_cbase[g + 1];
+        for (int64_t g = 0; g < nbg; g++) H->b_comms[g] = H->b_cbase[g + 1] - H->b_cbase[g];
+        HIPCHK(H, hipMemcpyAsync(cmin, H->b_cbase.data(), (size_t)nbg * 4, hipMemcpyHostToDevice, s));
+        int32_t mp = 0;
+        for (int32_t x : H->b_passes) mp = std::max(mp, x);
+        H->st.passes = mp;
+    }
     HIPCHK(H, hipStreamSynchronize(s));
     H->st.communities = H->ncom;
     return LOUVAIN_OK;
@@ -1038,10 +1297,10 @@ louvain_status louvain_run(louvain_t* h) {
     HIPCHK(h, hipEventRecord(e0, h->stream));
     Runner r(h);
     louvain_status st = r.run();
-    hipEventRecord(e1, h->stream);
-    hipEventSynchronize(e1);
+    (void)hipEventRecord(e1, h->stream);
+    (void)hipEventSynchronize(e1);
     float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (st != LOUVAIN_OK) { h->ran = false; return st; }
@@ -1078,12 +1337,58 @@ louvain_status louvain_get_membership(louvain_t* h, int32_t* out) {
     if (!h->ran) return fail(h, LOUVAIN_ERR_STATE, "louvain_run has not completed");
     if (h->g.n == 0) return LOUVAIN_OK;
     HIPCHK(h, hipMemcpyAsync(out, h->at<int32_t>(h->lay.C), h->g.n * 4, hipMemcpyDeviceToDevice, h->stream));
+    if (h->nb > 0)  // per-graph ids 0 .. communities - 1
+        launch_rebase(out, h->g.n, h->at<int32_t>(h->lay.gid0), h->at<int32_t>(h->lay.cmin), h->stream);
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_modularity_batch(louvain_t* h, double* q, int64_t* num, int64_t* den) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    if (h->nb <= 0) return fail(h, LOUVAIN_ERR_INVALID, "not a batched handle");
+    if (!h->ran) return fail(h, LOUVAIN_ERR_STATE, "louvain_run has not completed");
+    const int64_t n = h->g.n, G = h->nb;
+    i64* sigin = h->at<i64>(h->lay.K);
+    i64* sigtot = h->at<i64>(h->lay.Sig);
+    u64* gq = h->at<u64>(h->lay.gq);
+    if (n > 0) {
+        HIPCHK(h, hipMemsetAsync(sigin, 0, n * 8, h->stream));
+        HIPCHK(h, hipMemsetAsync(sigtot, 0, n * 8, h->stream));
+    }
+    HIPCHK(h, hipMemsetAsync(gq, 0, (size_t)G * 16, h->stream));
+    launch_modularity_arcs(h->L0, h->at<int32_t>(h->lay.C), sigin, sigtot, h->stream);
+    launch_mod_terms_batch(h->ncom, h->at<int32_t>(h->lay.cmin), G, h->at<u64>(h->lay.Wg), sigin, sigtot, gq,
+                           h->stream);
+    std::vector<u64> hq(2 * G);
+    louvain_status st = readback(h, hq.data(), gq, (size_t)G * 16);
+    if (st != LOUVAIN_OK) return st;
+    for (int64_t g = 0; g < G; g++) {
+        const i64 Wg = (i64)h->Wg[g];
+        __int128 numv = (__int128)(((unsigned __int128)hq[2 * g + 1] << 64) | hq[2 * g]);
+        __int128 denv = Wg == 0 ? (__int128)1 : (__int128)Wg * Wg;
+        if (Wg == 0) numv = 0;
+        if (num) { num[2 * g] = (int64_t)(numv >> 64); num[2 * g + 1] = (int64_t)(uint64_t)numv; }
+        if (den) { den[2 * g] = (int64_t)(denv >> 64); den[2 * g + 1] = (int64_t)(uint64_t)denv; }
+        if (q) q[g] = (double)numv / (double)denv;
+    }
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_batch_results(louvain_t* h, int32_t* passes, int32_t* iterations, int64_t* communities) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    if (h->nb <= 0) return fail(h, LOUVAIN_ERR_INVALID, "not a batched handle");
+    if (!h->ran) return fail(h, LOUVAIN_ERR_STATE, "louvain_run has not completed");
+    for (int64_t g = 0; g < h->nb; g++) {
+        if (passes) passes[g] = h->b_passes[g];
+        if (iterations) iterations[g] = h->b_iters[g];
+        if (communities) communities[g] = h->b_comms[g];
+    }
     return LOUVAIN_OK;
 }
 
 louvain_status louvain_modularity(louvain_t* h, double* q, int64_t num[2], int64_t den[2]) {
     if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    if (h->nb > 0) return fail(h, LOUVAIN_ERR_INVALID, "batched handle: use louvain_modularity_batch");
     if (!h->ran) return fail(h, LOUVAIN_ERR_STATE, "louvain_run has not completed");
     const int64_t n = h->g.n;
     i64* sigin = h->at<i64>(h->lay.K);

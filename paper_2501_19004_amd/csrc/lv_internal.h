@@ -58,6 +58,15 @@ struct MoveArgs {
     Ctl* ctl;
     int32_t* sdec;        // SYNC: per vertex of the queue, its decided target or -1
     int32_t bucket;       // bucket id for per-bucket counters
+    int32_t lstride;      // queue entries of this launch: list[slot * lstride + lphase]
+    int32_t lphase;
+    // batched ASYNC slices: slice seg_k of seg_ns takes, from every graph g's
+    // segment of the bucket's queue (start seg_start[g], length seg_cnt[g]),
+    // the entries [len*k/ns, len*(k+1)/ns); seg_pre[g] = slots of graphs < g
+    const int32_t* seg_pre;
+    const int32_t* seg_start;
+    const int32_t* seg_cnt;
+    int32_t seg_n, seg_k, seg_ns;
     const uint8_t* vbucket;
     // hub path (static hub list of the pass, ascending vertex id)
     const int32_t* hub_list;
@@ -70,6 +79,13 @@ struct MoveArgs {
     void* hub_vals;
     int32_t* hub_cnt;        // per static hub: occupied slots of its table (0 between iterations)
     int32_t* hub_slots;      // occupied slot lists: hub h's list starts at its table offset / 2
+    // batched runs (gid == nullptr for a single graph): graph id of every
+    // vertex of the level, per-graph total weight, graphs still moving in
+    // this pass, per-graph 128-bit gain sums (lo, hi)
+    const int32_t* gid;
+    const u64* Wg;
+    const uint8_t* gact;
+    u64* Sg;
     // per-vertex state of the learned pruner's features (learn = 1)
     int32_t learn;
     uint32_t itag;           // tag of this iteration, unique within the run
@@ -109,6 +125,9 @@ struct FusedLists {
     const int32_t* list[4];
     int32_t count[4];
     int64_t blk_pre[5];
+    const int32_t* seg_pre[4];    // batched slices: per-bucket rows (see MoveArgs)
+    const int32_t* seg_start[4];
+    const int32_t* seg_cnt[4];
 };
 
 struct Buckets {
@@ -131,7 +150,8 @@ void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int
 // Ordered partition of the level's vertices into NB_MOVE+1 bucket segments
 // (all vertices with arcs, or the flagged ones when use_flags); bucket totals
 // go to totals[0..NB_MOVE].  blkcnt/blkoff: (NB_MOVE+1) * bucket_blocks(n) (+1).
-void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags,
+void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags, const int32_t* gid,
+                        const uint8_t* gact,
                         int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
                         hipStream_t s);
 void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t count, i64* K, i64* Sig, Ctl* ctl,
@@ -155,6 +175,22 @@ void launch_mlp_zero(float* p, int64_t n, hipStream_t s);
 void launch_mlp_loss_grad(const float* w, const float* S, int64_t count, int64_t slots, int32_t batch, u64 seed,
                           int64_t step, float pos_weight, float* grad, double* loss, hipStream_t s);
 void launch_adam(float* w, const float* g, float* m, float* v, float lr, float bc1, float bc2, hipStream_t s);
+// batched slices: per-(bucket, graph) segment counts of the queue, their
+// starts, and for every slice the per-graph slot prefixes
+void launch_seg_count(const int32_t* list, int64_t len, const int32_t* gid, int32_t* segcnt, hipStream_t s);
+void launch_slice_prefix(const int32_t* segcnt, int nbt, int64_t count, int ns, int32_t* prefall, hipStream_t s);
+// ---- batched runs (lv_batch.hip)
+void launch_gid_init(const int64_t* vbase, int64_t count, int64_t n, int32_t* gid, hipStream_t s);
+void launch_graph_weights(const LevelView& L, const int32_t* gid, u64* Wg, Ctl* ctl, hipStream_t s);
+void launch_nonisolated_by_graph(const LevelView& L, const int32_t* gid, u64* out, hipStream_t s);
+void launch_used_by_graph(const int32_t* used, int64_t n, const int32_t* gid, u64* out, hipStream_t s);
+void launch_gid_next(const int32_t* used, const int32_t* newid, int64_t n, const int32_t* gid, int32_t* gid_next,
+                     hipStream_t s);
+void launch_graph_cmin(const int32_t* C, int64_t n, const int32_t* gid, int32_t* cmin, hipStream_t s);
+void launch_rebase(int32_t* C, int64_t n, const int32_t* gid, const int32_t* cmin, hipStream_t s);
+void launch_modularity_arcs(const LevelView& L0, const int32_t* C, i64* sigin, i64* sigtot, hipStream_t s);
+void launch_mod_terms_batch(int64_t ncom, const int32_t* cbase, int64_t count, const u64* Wg, const i64* sigin,
+                            const i64* sigtot, u64* qlohi, hipStream_t s);
 
 // ---- launchers: aggregation and modularity (lv_aggr.hip)
 struct AggArgs {

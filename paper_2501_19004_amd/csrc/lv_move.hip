@@ -146,7 +146,11 @@ struct VBucket {
 struct MarkBucket {
     const uint8_t* vb;
     const uint8_t* flags;
-    __device__ __forceinline__ int operator()(int64_t v) const { return flags[v] ? (int)vb[v] : 255; }
+    const int32_t* gid;   // batched runs: only vertices of graphs still moving
+    const uint8_t* gact;
+    __device__ __forceinline__ int operator()(int64_t v) const {
+        return (flags[v] && (!gid || gact[gid[v]])) ? (int)vb[v] : 255;
+    }
 };
 
 // K'[i] = sum of i's arc weights (self-loop once); Sigma'[i] = K'[i].
@@ -233,7 +237,7 @@ struct Decision {
 // by this lane (all cap slots, or the nlist slots listed in `list`), reduces
 // over the group; every lane returns the same result.
 template <int G, int MODE, typename KeyT, typename AccT>
-__device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* keys, const AccT* vals, int64_t cap,
+__device__ __forceinline__ Decision decide(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals, int64_t cap,
                                            int lane, bool active, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
                                            i64* s_v, i64* s_t, const int32_t* list = nullptr,
                                            int64_t nlist = 0) {
@@ -265,7 +269,7 @@ __device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* key
             if (d == EMPTY_KEY) continue;
             ++nd;
             if (d == c) { kic = vv[u]; continue; }
-            const KeyT key = (KeyT)a.W * vv[u] - (KeyT)Ki * ss[u];
+            const KeyT key = (KeyT)W * vv[u] - (KeyT)Ki * ss[u];
             if (bd == EMPTY_KEY || better(key, d, bk, bd)) { bk = key; bd = d; bv = vv[u]; }
         }
     }
@@ -276,7 +280,7 @@ __device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* key
     Decision r{-1, 0, kic, 0, reduce_sum<G>(nd, s_t), bd != EMPTY_KEY ? bv : 0, 0};
     if (active && bd != EMPTY_KEY) {
         const i64 Sc = ld_s<MODE>(&a.Sig[c]);
-        const KeyT stay = (KeyT)a.W * kic - (KeyT)Ki * (Sc - Ki);
+        const KeyT stay = (KeyT)W * kic - (KeyT)Ki * (Sc - Ki);
         const KeyT gk = bk - stay;
         r.positive = gk > 0;
         bool ok = gk > 0 && (!a.pl || bd < c);
@@ -297,10 +301,10 @@ __device__ __forceinline__ Decision decide(const MoveArgs& a, const int32_t* key
 // undone if it is no longer positive.  Concurrent joins of one community are
 // therefore each checked against the community as it really is.
 template <int MODE>
-__device__ __forceinline__ bool apply_async(const MoveArgs& a, int32_t i, int32_t c, i64 Ki, Decision& dcs) {
+__device__ __forceinline__ bool apply_async(const MoveArgs& a, i64 W, int32_t i, int32_t c, i64 Ki, Decision& dcs) {
     const i64 old_d = (i64)atomicAdd((u64*)&a.Sig[dcs.target], (u64)Ki);
     const i64 Sc = ld_s<MODE>(&a.Sig[c]);
-    const i128 g = (i128)a.W * (dcs.kid - dcs.kic) - (i128)Ki * ((i128)old_d - Sc + Ki);
+    const i128 g = (i128)W * (dcs.kid - dcs.kic) - (i128)Ki * ((i128)old_d - Sc + Ki);
     if (g > 0) {
         atomicAdd((u64*)&a.Sig[c], (u64)(-Ki));
         st_c<MODE>(&a.Cp[i], dcs.target);
@@ -362,6 +366,7 @@ struct MoveShm {
     i128 gain[32];
     int32_t dec[32];
     int32_t pos[32];
+    int32_t gi[32];
     i64 arcs[32], nd[32];
 };
 
@@ -376,8 +381,24 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t slot = blk * NG + grp;
-    const bool active = slot < count;
-    const int32_t i = active ? list[slot] : -1;
+    const bool listed = slot < count;
+    int32_t i = -1;
+    if (listed) {
+        int64_t e = slot * a.lstride + a.lphase;
+        if (a.seg_pre) {
+            int32_t lo = 0, hi = a.seg_n - 1;  // graph of this slot: largest g with seg_pre[g] <= slot
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (a.seg_pre[mid] <= slot) lo = mid; else hi = mid - 1;
+            }
+            const int64_t len = a.seg_cnt[lo];
+            e = a.seg_start[lo] + len * a.seg_k / a.seg_ns + (slot - a.seg_pre[lo]);
+        }
+        i = list[e];
+    }
+    const int32_t gi = (listed && a.gid) ? a.gid[i] : -1;  // batched runs: graph of i
+    const bool active = listed && (gi < 0 || a.gact[gi]);
+    const i64 Wi = gi >= 0 ? (i64)a.Wg[gi] : a.W;
     int32_t* keys = s_keys + grp * CAP;
     AccT* vals = s_vals + grp * CAP;
     for (int s = lane; s < CAP; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }
@@ -411,15 +432,15 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     group_sync<G>();
 
     Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, keys, vals, CAP, lane, active, c, Ki, sh.k64, sh.d, sh.v, sh.t)
-        : decide<G, MODE, i128, AccT>(a, keys, vals, CAP, lane, active, c, Ki, sh.k128, sh.d, sh.v, sh.t);
+        ? decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, sh.k64, sh.d, sh.v, sh.t)
+        : decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, sh.k128, sh.d, sh.v, sh.t);
 
     if (a.learn && active && lane == 0) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
-        if (lane == 0 && active) a.sdec[i] = dcs.target;
+        if (lane == 0 && listed) a.sdec[i] = dcs.target;  // -1 for a vertex of a graph that has converged
     } else {
         int32_t t = -1;
-        if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, i, c, Ki, dcs)) t = dcs.target;
+        if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, Wi, i, c, Ki, dcs)) t = dcs.target;
         t = group_bcast<G>(t, sh.x);
         if ((a.prune || a.learn) && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
     }
@@ -427,6 +448,7 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
         sh.gain[grp] = dcs.gain;
         sh.dec[grp] = dcs.target;
         sh.pos[grp] = active ? dcs.positive : 0;
+        sh.gi[grp] = gi;
         sh.arcs[grp] = active ? (o1 - o0) : -1;
         sh.nd[grp] = dcs.nd;
     }
@@ -443,6 +465,21 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
             if (sh.dec[k] >= 0) { sg += sh.gain[k]; nm++; nma += (u64)sh.arcs[k]; }
         }
         add_block_totals(a.ctl, bucket, ne, na, ndt, nm, nma, sg, np);
+        if (a.Sg) {
+            // per-graph gain sums, one 128-bit atomic per run of equal graph id
+            int32_t cur = -1;
+            i128 acc = 0;
+            for (int k = 0; k < NG; k++) {
+                if (sh.arcs[k] < 0 || sh.dec[k] < 0) continue;
+                if (sh.gi[k] != cur) {
+                    if (cur >= 0 && acc != 0) atomic_add_i128(&a.Sg[2 * cur], &a.Sg[2 * cur + 1], acc);
+                    cur = sh.gi[k];
+                    acc = 0;
+                }
+                acc += sh.gain[k];
+            }
+            if (cur >= 0 && acc != 0) atomic_add_i128(&a.Sg[2 * cur], &a.Sg[2 * cur + 1], acc);
+        }
     }
 }
 
@@ -467,29 +504,33 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
     int bk = 0;
     while (bk < 3 && b >= f.blk_pre[bk + 1]) bk++;
     const int64_t blk = b - f.blk_pre[bk];
+    MoveArgs aa = a;
+    aa.seg_pre = f.seg_pre[bk];
+    aa.seg_start = f.seg_start[bk];
+    aa.seg_cnt = f.seg_cnt[bk];
     switch (bk) {
         case 0: {
             constexpr int NG = 256 / MOVE_G[0];
             move_block<OffT, WK, AccT, MOVE_G[0], MOVE_CAP[0], MODE>(
-                a, f.list[0], f.count[0], blk, 0, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[0] * 4), sh);
+                aa, f.list[0], f.count[0], blk, 0, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[0] * 4), sh);
             break;
         }
         case 1: {
             constexpr int NG = 256 / MOVE_G[1];
             move_block<OffT, WK, AccT, MOVE_G[1], MOVE_CAP[1], MODE>(
-                a, f.list[1], f.count[1], blk, 1, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[1] * 4), sh);
+                aa, f.list[1], f.count[1], blk, 1, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[1] * 4), sh);
             break;
         }
         case 2: {
             constexpr int NG = 256 / MOVE_G[2];
             move_block<OffT, WK, AccT, MOVE_G[2], MOVE_CAP[2], MODE>(
-                a, f.list[2], f.count[2], blk, 2, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[2] * 4), sh);
+                aa, f.list[2], f.count[2], blk, 2, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[2] * 4), sh);
             break;
         }
         default: {
             constexpr int NG = 256 / MOVE_G[3];
             move_block<OffT, WK, AccT, MOVE_G[3], MOVE_CAP[3], MODE>(
-                a, f.list[3], f.count[3], blk, 3, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[3] * 4), sh);
+                aa, f.list[3], f.count[3], blk, 3, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[3] * 4), sh);
             break;
         }
     }
@@ -505,7 +546,7 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
 // iteration of a pass, or without pruning), else those flagged by the
 // previous iteration.
 __device__ __forceinline__ bool hub_queued(const MoveArgs& a, int32_t v) {
-    return a.all_queued || a.fcur[v];
+    return (a.all_queued || a.fcur[v]) && (!a.gid || a.gact[a.gid[v]]);
 }
 // largest h in [0, n) with pre[h] - base <= x
 __device__ __forceinline__ int32_t owner_of(const int64_t* pre, int32_t n, int64_t base, int64_t x) {
@@ -570,7 +611,10 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
     const int32_t v = a.hub_list[h];
     const int tid = threadIdx.x;
     if (!hub_queued(a, v)) {
-        if (tid == 0) a.gdec[h] = -1;
+        if (tid == 0) {
+            a.gdec[h] = -1;
+            if constexpr (MODE == M_SYNC) a.sdec[v] = -1;
+        }
         return;
     }
     const int64_t toff = a.hub_pre[h] - a.hub_pre[a.g_lo];
@@ -581,9 +625,11 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
     const int64_t nocc = a.hub_cnt[h];
     const int32_t c = ld_c<MODE>(&a.Cp[v]);
     const i64 Ki = a.K[v];
+    const int32_t gv = a.gid ? a.gid[v] : -1;
+    const i64 Wv = gv >= 0 ? (i64)a.Wg[gv] : a.W;
     Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k64, s_d, s_v, s_t, slots, nocc)
-        : decide<G, MODE, i128, AccT>(a, keys, vals, cap, tid, true, c, Ki, s_k128, s_d, s_v, s_t, slots, nocc);
+        ? decide<G, MODE, i64, AccT>(a, Wv, keys, vals, cap, tid, true, c, Ki, s_k64, s_d, s_v, s_t, slots, nocc)
+        : decide<G, MODE, i128, AccT>(a, Wv, keys, vals, cap, tid, true, c, Ki, s_k128, s_d, s_v, s_t, slots, nocc);
     // clean the occupied slots for the next iteration
     for (int64_t k = tid; k < nocc; k += G) {
         const int32_t sl = slots[k];
@@ -596,8 +642,9 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
         if constexpr (MODE == M_SYNC) {
             a.sdec[v] = dcs.target;
         } else {
-            if (dcs.target >= 0) apply_async<MODE>(a, v, c, Ki, dcs);
+            if (dcs.target >= 0) apply_async<MODE>(a, Wv, v, c, Ki, dcs);
         }
+        if (a.Sg && dcs.target >= 0) atomic_add_i128(&a.Sg[2 * gv], &a.Sg[2 * gv + 1], dcs.gain);
         if (a.learn) note_evaluation(a, v, dcs);
         a.gdec[h] = dcs.target;
         add_block_totals(a.ctl, a.bucket, 1, (u64)deg, (u64)dcs.nd, dcs.target >= 0 ? 1 : 0,
@@ -662,7 +709,8 @@ void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int
         k_classify<int32_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, B, vbucket, Cp, K, Sig);
 }
 
-void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags,
+void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags, const int32_t* gid,
+                        const uint8_t* gact,
                         int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
                         hipStream_t s) {
     constexpr int NB = NB_MOVE + 1;
@@ -672,7 +720,7 @@ void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags,
         return;
     }
     if (use_flags) {
-        MarkBucket bf{vbucket, flags};
+        MarkBucket bf{vbucket, flags, gid, gact};
         k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb);
         scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
         k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out);

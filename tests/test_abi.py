@@ -143,3 +143,26 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.louvain_run(None) == lv.LOUVAIN_ERR_INVALID
     assert lib.louvain_get_membership(None, None) == lv.LOUVAIN_ERR_INVALID
     lib.louvain_destroy(None)
+
+
+def test_batch_create_rejects_bad_arguments(lib):
+    fake = 4096
+    g = lv.LouvainGraph(10, 20, 32, fake, fake, None)
+    p = lv.louvain_params_default()
+    h = ctypes.c_void_p()
+
+    def create(vb, count, params=p):
+        arr = (ctypes.c_int64 * len(vb))(*vb)
+        return lib.louvain_create_batch(ctypes.byref(g), arr, count, ctypes.byref(params), None, None, 0,
+                                        ctypes.byref(h))
+    assert create([0, 5, 10], 0) == lv.LOUVAIN_ERR_INVALID      # count must be >= 1
+    assert create([0, 5, 9], 2) == lv.LOUVAIN_ERR_INVALID       # must end at n
+    assert create([0, 7, 5, 10], 3) == lv.LOUVAIN_ERR_INVALID   # non-decreasing
+    assert create([1, 5, 10], 2) == lv.LOUVAIN_ERR_INVALID      # must start at 0
+    learned = lv.louvain_params_default()
+    learned.pruner = lv.PRUNE_LEARNED
+    learned.pruner_weights = fake
+    assert create([0, 5, 10], 2, learned) == lv.LOUVAIN_ERR_INVALID
+    assert create([0, 5, 10], 2) == lv.LOUVAIN_ERR_WORKSPACE    # arguments fine, no workspace
+    single = lv.louvain_workspace_size(g, p)
+    assert lv.louvain_workspace_size_batch(g, 2, p) > single == lv.louvain_workspace_size_batch(g, 0, p)
