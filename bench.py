@@ -110,21 +110,78 @@ def learned_leg(lv, torch, g, off, idx, w, mode, args, q_plain, dt_plain):
     print(f"[bench] pruner: {S.shape[0]} samples ({pos:.3f} moved), loss {loss0:.4f} -> {loss:.4f}, "
           f"{t_train:.1f}s", file=sys.stderr, flush=True)
     extra = {} if args.async_coherent is None else {"async_coherent": args.async_coherent}
-    L = lv.Louvain(off, idx, w, mode=mode, pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
-                   pruner_threshold=args.threshold, guard_tolerance=1 if args.guard == "tolerance" else 0, **extra)
-    dt, q, st = timed_runs(L, args.steps, args.warmup)
-    L.close()
-    print(f"[bench] learned: {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), sweeps={st.sweeps} "
-          f"pruned={st.pruned} iterations={st.iterations}", file=sys.stderr, flush=True)
-    return {"value": round(g.nnz / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
-            "speedup_vs_plain": round(dt_plain / dt, 3), "modularity": round(q, 6),
-            "dq_vs_plain": round(q - q_plain, 6), "equal_modularity": abs(q - q_plain) <= 0.002,
-            "threshold": args.threshold, "guard": args.guard, "passes": st.passes, "iterations": st.iterations,
-            "sweeps": st.sweeps, "pruned": st.pruned, "vertices_evaluated": st.vertices_evaluated,
-            "arcs_scanned": st.arcs_scanned,
+    legs = {}
+    for guard in ("strict", "tolerance"):
+        L = lv.Louvain(off, idx, w, mode=mode, pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
+                       pruner_threshold=args.threshold, guard_tolerance=1 if guard == "tolerance" else 0, **extra)
+        dt, q, st = timed_runs(L, args.steps, args.warmup)
+        L.close()
+        print(f"[bench] learned ({guard} guard): {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), "
+              f"sweeps={st.sweeps} pruned={st.pruned} iterations={st.iterations}", file=sys.stderr, flush=True)
+        legs[guard] = {"value": round(g.nnz / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
+                       "speedup_vs_plain": round(dt_plain / dt, 3), "modularity": round(q, 6),
+                       "dq_vs_plain": round(q - q_plain, 6), "equal_modularity": abs(q - q_plain) <= 0.002,
+                       "passes": st.passes, "iterations": st.iterations, "sweeps": st.sweeps, "pruned": st.pruned,
+                       "vertices_evaluated": st.vertices_evaluated, "arcs_scanned": st.arcs_scanned}
+    return {"threshold": args.threshold, "strict_guard": legs["strict"], "tolerance_guard": legs["tolerance"],
             "training": {"graphs": "R-MAT scale 18, edge factor 16, seeds 1018-1020", "samples": int(S.shape[0]),
                          "positive_rate": round(pos, 4), "loss_initial": round(loss0, 5), "loss_final": round(loss, 5),
                          "steps": 1500, "batch": 4096, "lr": 3e-3, "seconds": round(t_train, 1)}}
+
+
+def batch_leg(lv, torch, args):
+    """Batched runs: SBM graphs (equal-size communities, 4 to 64 of them,
+    average degree uniform in [8, 32], intra/inter degree ratio 4, weights
+    uniform in [1, 4]) with vertex counts log-uniform in [200, nmax], graph k
+    generated with seed 4000 + k, all in one batched handle."""
+    import numpy as np
+    import graphgen as gg
+    t0 = time.time()
+    rng = np.random.default_rng(4)
+    graphs = []
+    for k in range(args.batch_graphs):
+        n = int(np.exp(rng.uniform(np.log(200), np.log(args.batch_nmax))))
+        graphs.append(gg.sbm_degree(n, int(rng.integers(4, 65)), float(rng.uniform(8, 32)), seed=4000 + k,
+                                    wmin=1, wmax=4))
+    off, idx, w, vbase = lv.batch_tensors(graphs, "cuda:0")
+    nv, na = int(vbase[-1]), int(idx.numel())
+    print(f"[bench] batch: {len(graphs)} SBM graphs, {nv} vertices, {na} arcs, built in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    out = {"workload": f"{len(graphs)} SBM graphs, vertices log-uniform in [200, {args.batch_nmax}], "
+                       f"4-64 communities, average degree U[8,32], intra/inter 4:1, weights U[1,4]",
+           "graphs": len(graphs), "vertices": nv, "arcs": na}
+    for mode, name in ((lv.ASYNC, "async"), (lv.SYNC, "sync")):
+        L = lv.Louvain(off, idx, w, vbase=vbase, mode=mode)
+        dt, _, _ = timed_batch(L, args.steps, args.warmup)
+        q = np.array(L.modularity_batch()[0])
+        passes, iters, comms = L.batch_results()
+        L.close()
+        out[name] = {"value": round(na / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
+                     "mean_modularity": round(float(q.mean()), 6), "max_passes": int(max(passes)),
+                     "max_iterations": int(max(iters))}
+        if not args.no_cpu_baseline:
+            # quality against the sequential oracle on the first 64 graphs
+            import oracle
+            d = []
+            for k, gk in enumerate(graphs[:64]):
+                gk.weights = gk.weights.astype(np.int64)
+                d.append(q[k] - oracle.modularity(gk, oracle.louvain(gk).membership))
+            out[name]["dq_vs_oracle_first64"] = {"mean": round(float(np.mean(d)), 6), "min": round(float(min(d)), 6)}
+        print(f"[bench] batch {name}: {dt * 1e3:.2f} ms/run, {na / dt / 1e6:.1f} M arcs/s, mean Q {q.mean():.4f}",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def timed_batch(L, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        L.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        L.run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / max(steps, 1), None, None
 
 
 def main():
@@ -138,6 +195,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-pruner leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-SBM leg")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-nmax", type=int, default=20000)
     ap.add_argument("--threshold", type=float, default=0.5, help="learned pruner: keep iff sigmoid >= threshold")
     ap.add_argument("--guard", default="strict", choices=["strict", "tolerance"],
                     help="learned pruner: a pass ends at a full sweep with no positive-gain move (strict) "
@@ -213,6 +273,9 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_leg(lv, torch, g, off, idx, w, mode, args, q, dt)
+    batch = None
+    if not args.no_batch:
+        batch = batch_leg(lv, torch, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -250,6 +313,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "learned_pruner": learned,
+        "batch": batch,
     }
     print(json.dumps(out))
     L.close()
