@@ -278,19 +278,22 @@ int64_t move_alg_bytes(const LevelView& L, uint64_t eval, uint64_t arcs, uint64_
     const int64_t offb = L.t.off64 ? 8 : 4;
     const int64_t wb = L.t.wk == 0 ? 0 : (L.t.wk == 1 ? 4 : 8);
     int64_t b = (int64_t)eval * (4 + 4 + 8 + 8 + 2 * offb) + (int64_t)arcs * (4 + 4 + wb) + (int64_t)distinct * 8;
-    if (sync) b += (int64_t)moves * 8;
-    else b += (int64_t)moves * (4 + 16) + (int64_t)marcs * (4 + 4 + 1);
+    // SYNC: one decision word per evaluated vertex (applied by k_sync_apply);
+    // ASYNC: C' write and two Sigma' atomics per move, then per arc of a
+    // mover its index and a flag byte
+    if (sync) b += (int64_t)eval * 4;
+    else b += (int64_t)moves * (4 + 16) + (int64_t)marcs * (4 + 1);
     // learned-pruner state: own/adv per evaluation, moved tag per move, a
     // moved-neighbour count per arc of a mover
     if (learn) b += (int64_t)eval * 16 + (int64_t)moves * 4 + (int64_t)marcs * 4;
     return b;
 }
 
-// Bytes of the learned filter: a stamp per vertex, the feature state of each
-// flagged vertex, an unstamp per dropped vertex, each recorded sample.
+// Bytes of the learned filter: a flag byte per vertex, the feature state of
+// each flagged vertex, a cleared flag per dropped vertex, each recorded sample.
 int64_t filter_alg_bytes(const LevelView& L, int64_t n, int64_t flagged, int64_t dropped, int64_t samples) {
     const int64_t offb = L.t.off64 ? 8 : 4;
-    return n * 4 + flagged * (8 + 8 + 8 + 4 + 4 + 2 * offb) + dropped * 4 + samples * 36;
+    return n * 1 + flagged * (8 + 8 + 8 + 4 + 4 + 2 * offb) + dropped * 1 + samples * 36;
 }
 
 // Sum of the striped per-iteration counters.
