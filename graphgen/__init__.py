@@ -23,7 +23,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "graphgen.c")
 _LIB = os.path.join(_HERE, "libgraphgen.so")
+_DEV_SRC = os.path.join(_HERE, "rmat_device.hip")
+_DEV_LIB = os.path.join(_HERE, "libgraphgen_hip.so")
 _lib = None
+_dev_lib = None
 
 
 def build(force: bool = True) -> str:
@@ -34,6 +37,37 @@ def build(force: bool = True) -> str:
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_device(force: bool = True) -> str:
+    """Compile libgraphgen_hip.so (the device R-MAT tuple generator) for gfx950."""
+    if force or not os.path.exists(_DEV_LIB):
+        tmp = _DEV_LIB + ".tmp"
+        hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+        subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-o", tmp, "-x", "hip", _DEV_SRC],
+                              stderr=subprocess.DEVNULL if os.environ.get("GG_QUIET") else None)
+        os.replace(tmp, _DEV_LIB)
+    return _DEV_LIB
+
+
+def _load_device():
+    global _dev_lib
+    if _dev_lib is None:
+        if not os.path.exists(_DEV_LIB):
+            raise RuntimeError(f"{_DEV_LIB} is not built (graphgen.build_device())")
+        lib = ctypes.CDLL(_DEV_LIB)
+        vp = ctypes.c_void_p
+        lib.gg_dev_rmat_hist.restype = ctypes.c_int
+        lib.gg_dev_rmat_hist.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_uint64, vp, ctypes.c_int, vp, vp]
+        lib.gg_dev_rmat_select.restype = ctypes.c_int
+        lib.gg_dev_rmat_select.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_uint64, vp, ctypes.c_int, ctypes.c_int64,
+                                           ctypes.c_int64, vp, ctypes.c_int64, vp, vp]
+        _dev_lib = lib
+    return _dev_lib
 
 
 def _load():
@@ -58,6 +92,8 @@ def _load():
                                     ctypes.c_uint64, ctypes.c_int, u64p, ctypes.c_int64, i32p]
         lib.gg_erdos_keys.restype = ctypes.c_int64
         lib.gg_erdos_keys.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, u64p, ctypes.c_int64]
+        lib.gg_perm.restype = None
+        lib.gg_perm.argtypes = [ctypes.c_int64, ctypes.c_uint64, i32p]
         lib.gg_csr_from_keys.restype = None
         lib.gg_csr_from_keys.argtypes = [ctypes.c_int64, ctypes.c_int64, u64p, ctypes.c_uint64,
                                          ctypes.c_int32, ctypes.c_int32, i64p, i32p, i32p]
@@ -122,6 +158,123 @@ def rmat(scale: int, edge_factor: int, a=0.57, b=0.19, c=0.19, seed: int = 22, p
     if m < 0:
         raise MemoryError("R-MAT generation failed")
     return _from_keys(n, keys, m, seed, wmin, wmax, f"rmat-s{scale}-ef{edge_factor}-seed{seed}")
+
+
+_M64 = (1 << 64) - 1
+_ST_RMAT = 1
+
+
+def _mix64(z: int) -> int:
+    z = (z + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def rmat_device(scale: int, edge_factor: int, a=0.57, b=0.19, c=0.19, seed: int = 22, permute: bool = True,
+                device="cuda", round_cap: int = 1 << 28):
+    """R-MAT graph built on the GPU: the same graph as ``rmat`` (unit weights).
+
+    Returns (offsets int64 [n+1], indices int32 [nnz]) as device tensors.  The
+    tuples are drawn on the device from the same counter-based stream as the
+    host generator; keys are collected in rounds of at most ``round_cap``
+    (by ranges of the smaller endpoint), sorted and deduplicated per round,
+    then laid out as a symmetric CSR with ascending rows, again in rounds of
+    at most ``round_cap`` arcs.  Peak device memory is about
+    8 B x unique edges + 4 B x arcs + a few x 8 B x round_cap.
+    """
+    import torch
+
+    lib = _load_device()
+    n = 1 << scale
+    nt = edge_factor * n
+    dev = torch.device(device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    perm_d = None
+    if permute:
+        perm = np.empty(n, dtype=np.int32)
+        _load().gg_perm(n, seed, _ptr(perm, ctypes.c_int32))
+        perm_d = torch.from_numpy(perm).to(dev)
+        del perm
+    pptr = ctypes.c_void_p(perm_d.data_ptr() if perm_d is not None else 0)
+    base = _mix64(seed ^ _mix64(_ST_RMAT))
+    ab = a + b
+    abc = a + b + c
+    shift = max(0, scale - 12)
+    nbins = 1 << (scale - shift)
+    hist = torch.zeros(nbins, dtype=torch.int64, device=dev)
+    if lib.gg_dev_rmat_hist(scale, nt, a, ab, abc, base, pptr, shift, ctypes.c_void_p(hist.data_ptr()), stream):
+        raise RuntimeError("device R-MAT histogram failed")
+    h = hist.cpu().numpy()
+    if h.max(initial=0) > round_cap:
+        raise RuntimeError("one R-MAT key bin exceeds round_cap; raise round_cap")
+    rounds, lo, acc = [], 0, 0
+    for bi in range(nbins):
+        if acc + h[bi] > round_cap:
+            rounds.append((lo, bi))
+            lo, acc = bi, 0
+        acc += int(h[bi])
+    rounds.append((lo, nbins))
+    buf = torch.empty(min(round_cap, max(1, int(h.sum()))), dtype=torch.int64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    uniq = []
+    for blo, bhi in rounds:
+        expect = int(h[blo:bhi].sum())
+        if expect == 0:
+            continue
+        cnt.zero_()
+        if lib.gg_dev_rmat_select(scale, nt, a, ab, abc, base, pptr, shift, blo, bhi,
+                                  ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.c_void_p(cnt.data_ptr()),
+                                  stream):
+            raise RuntimeError("device R-MAT selection failed")
+        k = int(cnt.item())
+        if k != expect:
+            raise RuntimeError(f"device R-MAT round found {k} keys, histogram said {expect}")
+        keys = torch.sort(buf[:k]).values
+        uniq.append(torch.unique_consecutive(keys))
+        del keys
+    del buf, perm_d
+    mask = n - 1
+    deg = torch.zeros(n, dtype=torch.int64, device=dev)
+    for u in uniq:
+        deg += torch.bincount(u >> scale, minlength=n)
+        deg += torch.bincount(u & mask, minlength=n)
+    off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    off[1:] = torch.cumsum(deg, 0)
+    del deg
+    nnz = int(off[-1].item())
+    idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    offh = off.cpu().numpy()
+    r0 = 0
+    while r0 < n:
+        # rows [r0, r1) with at most round_cap arcs (at least one row)
+        r1 = int(np.searchsorted(offh, offh[r0] + round_cap, side="right")) - 1
+        r1 = min(n, max(r1, r0 + 1))
+        parts = []
+        for u in uniq:
+            src = u >> scale
+            dst = u & mask
+            up = u[(src >= r0) & (src < r1)]
+            if up.numel():
+                parts.append(up)
+            sel = (dst >= r0) & (dst < r1)
+            low = u[sel]
+            if low.numel():
+                parts.append(((low & mask) << scale) | (low >> scale))
+            del src, dst, sel, up, low
+        e0, e1 = int(offh[r0]), int(offh[r1])
+        if parts:
+            arcs = torch.sort(torch.cat(parts)).values
+            if arcs.numel() != e1 - e0:
+                raise RuntimeError("device R-MAT CSR round size mismatch")
+            idx[e0:e1] = (arcs & mask).to(torch.int32)
+            del arcs
+        elif e1 != e0:
+            raise RuntimeError("device R-MAT CSR round size mismatch")
+        del parts
+        r0 = r1
+    del uniq
+    return off, idx
 
 
 def grid(rows: int, cols: int, p_del: float = 0.1, p_diag: float = 0.01, wmin: int = 1, wmax: int = 16,

@@ -102,6 +102,9 @@ static void make_perm(int64_t n, uint64_t seed, int32_t* perm) {
     }
 }
 
+/* Exported permutation (the R-MAT relabelling) for the device generator. */
+void gg_perm(int64_t n, uint64_t seed, int32_t* perm) { make_perm(n, seed, perm); }
+
 /*
  * Symmetric CSR from sorted unique keys u*n+v (u < v).  Rows come out sorted:
  * the lower neighbours (keys with v == row) are placed first in key order,

@@ -43,7 +43,7 @@ inline uint64_t next_pow2(uint64_t x) {
 struct Layout {
     size_t ctl, seg, C, Cp, K, Sig, mark, vbucket, blist, qa, qb, sdec, hcaps, hpre;
     size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
-    size_t hidx, hw, sup_off[2], sup_idx[2], sup_w[2], pool_keys, pool_vals, scan;
+    size_t hidx, hw, sup_off, sup_idx, sup_w, pool_keys, pool_vals, scan;
     size_t md, mpos, bnch, bchpre, bitmaps, gdec, blkcnt, blkoff;
     size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots;
     // batched runs (count graphs; absent for a single graph)
@@ -84,11 +84,11 @@ bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
     L->rowlen = take((N + 1) * 4);
     L->hidx = take(M * 4);
     L->hw = take(M * 8);
-    for (int k = 0; k < 2; k++) {
-        L->sup_off[k] = take((N + 1) * 8);
-        L->sup_idx[k] = take(M * 4);
-        L->sup_w[k] = take(M * 8);
-    }
+    // One super-graph buffer: level p+1 is compacted over level p, which the
+    // hashing into the holey buffer has finished reading by then.
+    L->sup_off = take((N + 1) * 8);
+    L->sup_idx = take(M * 4);
+    L->sup_w = take(M * 8);
     int64_t pool = (int64_t)next_pow2(2 * (uint64_t)(n + 1));
     int64_t want = std::min<int64_t>(std::max<int64_t>(2 * m, (int64_t)1 << 20), (int64_t)1 << 28);
     pool = std::max(pool, want);
@@ -601,7 +601,6 @@ louvain_status Runner::run() {
     iota_i32(C, n0, s);
 
     LevelView L = H->L0;
-    int cur_sup = 0;
     bool stopped_before_aggregate = false;
     bool have_newid = false;
     int64_t ncom_last = 0;
@@ -1127,7 +1126,6 @@ louvain_status Runner::run() {
         for (int b = 0; b < NBA; b++) asegs[b + 1] = asegs[b] + acount[b];
 
         // ---------------- super-row hashing into the holey buffer
-        const int nxt = cur_sup ^ 1;
         AggArgs A{};
         A.Cp = Cp;
         A.coff = coff;
@@ -1198,9 +1196,9 @@ louvain_status Runner::run() {
             }
         }
         // ---------------- compaction into the next super-graph
-        void* goff = at<void>(Y.sup_off[nxt]);
-        int32_t* gidx = at<int32_t>(Y.sup_idx[nxt]);
-        void* gw = at<void>(Y.sup_w[nxt]);
+        void* goff = at<void>(Y.sup_off);
+        int32_t* gidx = at<int32_t>(Y.sup_idx);
+        void* gw = at<void>(Y.sup_w);
         launch_rowlen_to_offsets(at<int32_t>(Y.rowlen), ncom, goff, H->sup_off64, scan, s);
         int64_t nnz2 = 0;
         if (H->sup_off64) {
@@ -1221,7 +1219,6 @@ louvain_status Runner::run() {
         L.t.off64 = H->sup_off64;
         L.t.wk = H->sup_wk;
         L.t.acc64 = 0;
-        cur_sup = nxt;
         gsel ^= 1;
         stopped_before_aggregate = false;
         have_newid = false;

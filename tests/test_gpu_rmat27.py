@@ -1,0 +1,129 @@
+"""R-MAT scale 27, edge factor 28 (134M vertices, about 6.5 billion arcs after
+deduplication, int64 offsets, unit weights) on one GPU, at full size.
+
+The oracle cannot run this graph in test time, so it checks sampled outputs
+one by one and the run is checked through properties that hold at any size:
+* SYNC, first local-moving iteration (identity membership, Sigma = K): the
+  decision of every sampled vertex equals the oracle's single-vertex decision
+  routine, evaluated on the vertex's own row (the decision depends only on the
+  row, the neighbours' K and W);
+* ASYNC, full run: community ids are dense and the reported modularity equals
+  Eq. 1 of the returned membership evaluated exactly with integer tensor
+  arithmetic, independently of the library.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lv = pytest.importorskip("paper_2501_19004_amd")
+
+SCALE, EF, SEED = 27, 28, 27
+
+
+@pytest.fixture(scope="module")
+def rmat27():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"[case] generating R-MAT scale {SCALE} ef {EF} seed {SEED} on the device", flush=True)
+    off, idx = gg.rmat_device(SCALE, EF, seed=SEED, device="cuda:0")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(f"[case] n={off.numel() - 1} arcs={idx.numel()}", flush=True)
+    yield off, idx
+    del off, idx
+    torch.cuda.empty_cache()
+
+
+def star_decision(W, i, nbrs, K):
+    """Oracle decision of vertex i in the first iteration, from its row alone:
+    a graph holding only i's row, ids relabelled in increasing order (so the
+    smallest-id tie rule is unchanged), Sigma of each singleton = its K."""
+    ids = np.unique(np.concatenate([nbrs, [i]]).astype(np.int64))
+    li = int(np.searchsorted(ids, i))
+    n = ids.size
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[li + 1:] = nbrs.size
+    idx = np.searchsorted(ids, nbrs).astype(np.int32)
+    g = gg.CSRGraph(n, off, idx, np.ones(nbrs.size, dtype=np.int64))
+    d, gain = oracle.best_move(g, W, np.arange(n, dtype=np.int32), K[ids].astype(np.int64), li)
+    return int(ids[d]) if (d is not None and gain > 0) else int(i)
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_sync_first_iteration_sampled_rmat27(rmat27):
+    off, idx = rmat27
+    L = lv.Louvain(off, idx, None, mode=lv.SYNC, max_passes=1, max_iterations=1)
+    first = {}
+
+    def on_iter(p, t, cp, sig, m, gain):
+        if p == 0 and t == 0:
+            first["cp"] = cp
+            first["sig"] = sig
+    L.trace(on_iter, None)
+    L.run()
+    L.close()
+    del L
+    torch.cuda.empty_cache()
+    cp = first["cp"]
+    offh = off.cpu().numpy()
+    deg = np.diff(offh)
+    W = int(offh[-1])
+    assert int(first["sig"].sum()) == W
+    rng = np.random.default_rng(27)
+    big = np.flatnonzero((deg > 4096) & (deg <= 20000))
+    sample = np.concatenate([rng.choice(big, min(40, big.size), replace=False),
+                             rng.choice(np.flatnonzero(deg > 0), 1500, replace=False)])
+    for i in sample:
+        nbrs = idx[int(offh[i]):int(offh[i + 1])].cpu().numpy()
+        expect = star_decision(W, int(i), nbrs, deg)
+        assert cp[i] == expect, (int(i), int(deg[i]), int(cp[i]), expect)
+
+
+def exact_modularity_parts(off, idx, memb, n):
+    """(num, den) of Eq. 1 times W^2 for unit weights, exact: num = W * sum of
+    intra-community arc weight - sum_c K_c^2, den = W^2."""
+    dev = off.device
+    deg = (off[1:] - off[:-1]).to(torch.int64)
+    W = int(off[-1].item())
+    assert W < (1 << 33)
+    intra = 0
+    step = 1 << 22
+    for r0 in range(0, n, step):
+        r1 = min(n, r0 + step)
+        e0, e1 = int(off[r0].item()), int(off[r1].item())
+        if e1 == e0:
+            continue
+        src = torch.repeat_interleave(torch.arange(r0, r1, device=dev), deg[r0:r1])
+        intra += int((memb[src] == memb[idx[e0:e1].long()]).sum().item())
+    Kc = torch.zeros(n, dtype=torch.int64, device=dev)
+    Kc.index_add_(0, memb.long(), deg)
+    # K_c < 2^33: split K_c = a * 2^16 + b so every partial sum fits in int64
+    a, b = Kc >> 16, Kc & 0xFFFF
+    s2 = (int((a * a).sum().item()) << 32) + (int((2 * a * b).sum().item()) << 16) + int((b * b).sum().item())
+    return W * intra - s2, W * W
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_async_rmat27(rmat27):
+    off, idx = rmat27
+    n = off.numel() - 1
+    L = lv.Louvain(off, idx, None, mode=lv.ASYNC)
+    L.run()
+    st = L.stats()
+    q, num, den = L.modularity()
+    memb = L.membership()
+    L.close()
+    del L
+    torch.cuda.empty_cache()
+    print(f"[case] rmat27 ASYNC: Q={q:.5f} passes={st.passes} iterations={st.iterations} "
+          f"communities={st.communities}", flush=True)
+    assert int(memb.min().item()) == 0 and int(memb.max().item()) == st.communities - 1
+    assert int(torch.bincount(memb.long()).min().item()) >= 1
+    enum, eden = exact_modularity_parts(off, idx, memb.to(torch.int32), n)
+    assert num * eden == enum * den, (num, den, enum, eden)
+    assert q > 0.3
