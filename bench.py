@@ -121,6 +121,8 @@ def learned_leg(lv, torch, nnz, off, idx, w, mode, args, q_plain, dt_plain):
                        pruner_threshold=args.threshold, guard_tolerance=1 if guard == "tolerance" else 0, **extra)
         dt, q, st = timed_runs(L, args.steps, args.warmup)
         L.close()
+        del L
+        torch.cuda.empty_cache()
         print(f"[bench] learned ({guard} guard): {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), "
               f"sweeps={st.sweeps} pruned={st.pruned} iterations={st.iterations}", file=sys.stderr, flush=True)
         legs[guard] = {"value": round(nnz / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),

@@ -423,9 +423,13 @@ class Louvain:
         return louvain_sample_count(self.h)
 
     def close(self):
+        """Destroy the handle and release the workspace (the graph tensors stay
+        with the caller)."""
         if getattr(self, "h", None):
             louvain_destroy(self.h)
             self.h = None
+        self.workspace = None
+        self._keep = None
 
     def __del__(self):
         try:

@@ -45,7 +45,8 @@ struct Layout {
     size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
     size_t hidx, hw, sup_off, sup_idx, sup_w, pool_keys, pool_vals, scan;
     size_t md, mpos, bnch, bchpre, bitmaps, gdec, blkcnt, blkoff;
-    size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots;
+    size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots, hpart;
+    int64_t part_cap;
     // batched runs (count graphs; absent for a single graph)
     size_t gid[2], gid0, Wg, gact, Sg, gcnt, cmin, vbase, gq, segcnt, segstart, prefall;
     int64_t bitmap_words;
@@ -97,6 +98,10 @@ bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
     L->pool_vals = take((size_t)pool * 8);
     L->hslots = take((size_t)pool / 2 * 4);
     L->hcnt = take((N + 1) * 4);
+    // hub-decide partials: a launch never exceeds part_cap blocks, and no hub
+    // has more insert chunks than that
+    L->part_cap = (int64_t)(M / HUB_CH) + 2;
+    L->hpart = take((size_t)L->part_cap * sizeof(HubPart));
     if (count > 0) {
         const size_t G = (size_t)count;
         L->gid[0] = take(N * 4);
@@ -749,6 +754,7 @@ louvain_status Runner::run() {
             a.hub_vals = at<void>(Y.pool_vals);
             a.hub_cnt = at<int32_t>(Y.hcnt);
             a.hub_slots = at<int32_t>(Y.hslots);
+            a.hub_part = at<HubPart>(Y.hpart);
             a.gid = gid;
             a.Wg = Wg_dev;
             a.gact = gact_dev;
@@ -769,10 +775,25 @@ louvain_status Runner::run() {
                     if (lo >= hi) continue;
                     a.g_lo = lo;
                     a.g_hi = hi;
+                    a.tab_lo = lo;
                     const int64_t nchunks = hch_pre[hi] - hch_pre[lo];
                     if (decide_phase) {
                         timed(H, K_MOVE_HUB, 0, [&] { launch_hub_insert(LM, mode, a, nchunks, s); });
-                        timed(H, K_HUB_DECIDE, 0, [&] { launch_hub_decide(LM, mode, a, s); });
+                        // decide launches of at most part_cap blocks (all blocks of a hub in one launch)
+                        for (int32_t sl = lo; sl < hi;) {
+                            int32_t sh = sl + 1;
+                            while (sh < hi && hch_pre[sh + 1] - hch_pre[sl] <= Y.part_cap) sh++;
+                            MoveArgs ad = a;
+                            ad.g_lo = sl;
+                            ad.g_hi = sh;
+                            timed(H, K_HUB_DECIDE, 0, [&] {
+                                launch_hub_decide(LM, mode, ad, hch_pre[sh] - hch_pre[sl], s);
+                                launch_hub_final(LM, mode, ad, s);
+                            });
+                            sl = sh;
+                        }
+                        a.g_lo = lo;
+                        a.g_hi = hi;
                     }
                     if (mark_phase && (prune || learn))
                         timed(H, K_HUB_MARK, 0, [&] { launch_hub_mark(L, a, nchunks, s); });

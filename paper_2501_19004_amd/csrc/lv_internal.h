@@ -41,6 +41,14 @@ struct LevelView {
 };
 
 // Per-iteration arguments of the local-moving kernels.
+// Partial best candidate of one hub-decide block (a slice of the hub's
+// occupied slots); the hub's last block combines them.
+struct HubPart {
+    i64 klo, khi;  // key, as a 128-bit value
+    i64 v, kic, nd;
+    int32_t d, pad;
+};
+
 struct MoveArgs {
     const void* off;
     const int32_t* idx;
@@ -72,13 +80,15 @@ struct MoveArgs {
     const int32_t* hub_list;
     const int64_t* hub_pre;  // prefix of table capacities over the static list
     const int64_t* hch_pre;  // prefix of insert-chunk counts over the static list
-    int32_t g_lo, g_hi;      // hubs of this launch group (their tables fit the pool together)
+    int32_t g_lo, g_hi;      // hubs of this launch (their tables fit the pool together)
+    int32_t tab_lo;          // hub whose table starts the pool (tables sit at hub_pre[h] - hub_pre[tab_lo])
     int32_t all_queued;      // 1: every hub is queued (sweep, first iteration or no pruning)
     int32_t* gdec;           // per static hub: applied (ASYNC) or recorded (SYNC) target, or -1
     int32_t* hub_keys;
     void* hub_vals;
     int32_t* hub_cnt;        // per static hub: occupied slots of its table (0 between iterations)
     int32_t* hub_slots;      // occupied slot lists: hub h's list starts at its table offset / 2
+    HubPart* hub_part;       // partial decisions, one per decide block of the launch
     // batched runs (gid == nullptr for a single graph): graph id of every
     // vertex of the level, per-graph total weight, graphs still moving in
     // this pass, per-graph 128-bit gain sums (lo, hi)
@@ -162,7 +172,8 @@ void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int
 void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, const int32_t* list, int32_t count,
                  hipStream_t s);
 void launch_hub_insert(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s);
-void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s);
+void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s);
+void launch_hub_final(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s);
 void launch_hub_mark(const LevelView& L, const MoveArgs& a, int64_t nchunks, hipStream_t s);
 void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const FusedLists& f, hipStream_t s);
 void launch_sync_apply(const LevelView& L, const MoveArgs& a, const int32_t* list, int64_t count, hipStream_t s);

@@ -233,14 +233,22 @@ struct Decision {
     int32_t positive;  // the best candidate's gain was positive (before Pick-Less)
 };
 
-// Per-group decision after the table is filled.  Scans the table slots owned
-// by this lane (all cap slots, or the nlist slots listed in `list`), reduces
-// over the group; every lane returns the same result.
+// Best candidate of a group's table: the largest key W*K_{i->d} - K_i*Sigma_d
+// over the communities d != c (ties to the smaller d), with K_{i->c} and the
+// number of distinct communities.  bd = EMPTY_KEY when there is no candidate.
+template <typename KeyT>
+struct Best {
+    KeyT bk;
+    int32_t bd;
+    i64 bv, kic, nd;
+};
+
+// Scans the table slots owned by this lane (all cap slots, or the nlist slots
+// listed in `list`) and reduces over the group; every lane returns the same.
 template <int G, int MODE, typename KeyT, typename AccT>
-__device__ __forceinline__ Decision decide(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals, int64_t cap,
-                                           int lane, bool active, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
-                                           i64* s_v, i64* s_t, const int32_t* list = nullptr,
-                                           int64_t nlist = 0) {
+__device__ __forceinline__ Best<KeyT> scan_table(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals,
+                                                 int64_t cap, int lane, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
+                                                 i64* s_v, i64* s_t, const int32_t* list, int64_t nlist) {
     KeyT bk = 0;
     int32_t bd = EMPTY_KEY;
     i64 bv = 0, kic = 0, nd = 0;
@@ -277,22 +285,42 @@ __device__ __forceinline__ Decision decide(const MoveArgs& a, i64 W, const int32
     if (bd == EMPTY_KEY) bk = (sizeof(KeyT) == 8) ? (KeyT)INT64_MIN : (KeyT)(((i128)1) << 127);
     reduce_best<G, KeyT>(bk, bd, bv, s_k, s_d, s_v);
     kic = reduce_max<G>(kic, s_t);
-    Decision r{-1, 0, kic, 0, reduce_sum<G>(nd, s_t), bd != EMPTY_KEY ? bv : 0, 0};
-    if (active && bd != EMPTY_KEY) {
+    nd = reduce_sum<G>(nd, s_t);
+    return Best<KeyT>{bk, bd, bd != EMPTY_KEY ? bv : 0, kic, nd};
+}
+
+// The move of vertex i (community c) from its best candidate: the gain
+// against staying, Pick-Less, and (concurrent modes) the minimum-label rule.
+template <int MODE, typename KeyT>
+__device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bool active, int32_t c, i64 Ki,
+                                                    const Best<KeyT>& b) {
+    Decision r{-1, 0, b.kic, 0, b.nd, b.bd != EMPTY_KEY ? b.bv : 0, 0};
+    if (active && b.bd != EMPTY_KEY) {
         const i64 Sc = ld_s<MODE>(&a.Sig[c]);
-        const KeyT stay = (KeyT)W * kic - (KeyT)Ki * (Sc - Ki);
-        const KeyT gk = bk - stay;
+        const KeyT stay = (KeyT)W * b.kic - (KeyT)Ki * (Sc - Ki);
+        const KeyT gk = b.bk - stay;
         r.positive = gk > 0;
-        bool ok = gk > 0 && (!a.pl || bd < c);
+        bool ok = gk > 0 && (!a.pl || b.bd < c);
         if constexpr (MODE != M_SYNC) {
             // i alone in c, d a single-vertex community of larger id: let d's vertex come to c instead
-            if (ok && a.min_label && bd > c && Sc == Ki && ld_c<MODE>(&a.Cp[bd]) == bd &&
-                ld_s<MODE>(&a.Sig[bd]) == a.K[bd])
+            if (ok && a.min_label && b.bd > c && Sc == Ki && ld_c<MODE>(&a.Cp[b.bd]) == b.bd &&
+                ld_s<MODE>(&a.Sig[b.bd]) == a.K[b.bd])
                 ok = false;
         }
-        if (ok) { r.target = bd; r.kid = bv; r.gain = (i128)gk; }
+        if (ok) { r.target = b.bd; r.kid = b.bv; r.gain = (i128)gk; }
     }
     return r;
+}
+
+// Per-group decision after the table is filled.
+template <int G, int MODE, typename KeyT, typename AccT>
+__device__ __forceinline__ Decision decide(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals, int64_t cap,
+                                           int lane, bool active, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
+                                           i64* s_v, i64* s_t, const int32_t* list = nullptr,
+                                           int64_t nlist = 0) {
+    const Best<KeyT> b = scan_table<G, MODE, KeyT, AccT>(a, W, keys, vals, cap, lane, c, Ki, s_k, s_d, s_v, s_t,
+                                                         list, nlist);
+    return finish_decision<MODE, KeyT>(a, W, active, c, Ki, b);
 }
 
 // ASYNC move with validation: Sigma of the target is updated by an atomic
@@ -562,8 +590,10 @@ template <typename OffT, int WK, typename AccT, int MODE>
 __global__ void __launch_bounds__(1024) k_hub_insert(MoveArgs a) {
     constexpr int G = 1024;
     constexpr int L2C = Log2<HUB_LCAP>::v;
+    constexpr int PER = HUB_LCAP / G;
     __shared__ int32_t s_keys[HUB_LCAP];
     __shared__ AccT s_vals[HUB_LCAP];
+    __shared__ int32_t s_claim[2];  // claimed global slots of this block, their base in the hub's list
     const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
     const int32_t ng = a.g_hi - a.g_lo;
     const int64_t chunk_base = a.hch_pre[a.g_lo];
@@ -575,70 +605,89 @@ __global__ void __launch_bounds__(1024) k_hub_insert(MoveArgs a) {
     const i64 e0 = (i64)g.off[v] + k * HUB_CH;
     const i64 e1 = min(e0 + (i64)HUB_CH, (i64)g.off[v + 1]);
     for (int s = tid; s < HUB_LCAP; s += G) { s_keys[s] = EMPTY_KEY; s_vals[s] = 0; }
+    if (tid == 0) s_claim[0] = 0;
     __syncthreads();
-    for (i64 e = e0 + tid; e < e1; e += G) {
-        const int32_t j = g.idx[e];
-        if (j == v) continue;
-        const int32_t d = ld_c<MODE>(&a.Cp[j]);
-        table_add<AccT>(s_keys, s_vals, HUB_LCAP - 1, hash_slot<L2C>(d), d, (AccT)g.weight(e));
+    // U arcs per round: their index loads, then their C' gathers, are issued together.
+    constexpr int U = 4;
+    for (i64 eb = e0 + tid; eb < e1; eb += U * G) {
+        int32_t jj[U], dd[U];
+        AccT ww[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const i64 e = eb + (i64)u * G;
+            jj[u] = e < e1 ? g.idx[e] : v;
+            ww[u] = e < e1 ? (AccT)g.weight(e) : (AccT)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) dd[u] = jj[u] != v ? ld_c<MODE>(&a.Cp[jj[u]]) : EMPTY_KEY;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (dd[u] != EMPTY_KEY) table_add<AccT>(s_keys, s_vals, HUB_LCAP - 1, hash_slot<L2C>(dd[u]), dd[u], ww[u]);
     }
     __syncthreads();
-    const int64_t toff = a.hub_pre[h] - a.hub_pre[a.g_lo];
+    const int64_t toff = a.hub_pre[h] - a.hub_pre[a.tab_lo];
     const int64_t cap = a.hub_pre[h + 1] - a.hub_pre[h];
     const int log2cap = __ffsll((long long)cap) - 1;
+    const uint32_t mask = (uint32_t)(cap - 1);
     int32_t* keys = a.hub_keys + toff;
     AccT* vals = (AccT*)a.hub_vals + toff;
     int32_t* slots = a.hub_slots + toff / 2;  // cap >= 2 * distinct keys, so cap / 2 list entries suffice
-    for (int s = tid; s < HUB_LCAP; s += G) {
-        const int32_t d = s_keys[s];
-        if (d == EMPTY_KEY) continue;
-        const int64_t got = table_add_claim<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d,
-                                                  s_vals[s]);
-        if (got >= 0) slots[atomicAdd(&a.hub_cnt[h], 1)] = (int32_t)got;
+    // Merge into the hub's table: the first probes of all of this thread's
+    // keys are issued together; a key whose home slot holds another key
+    // continues along its probe sequence.
+    int32_t kk[PER], old[PER];
+    uint32_t home[PER];
+    int64_t got[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) kk[u] = s_keys[tid + u * G];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        home[u] = kk[u] != EMPTY_KEY ? hash_slot_rt(kk[u], log2cap) : 0u;
+        old[u] = kk[u] != EMPTY_KEY ? atomicCAS(&keys[home[u]], EMPTY_KEY, kk[u]) : EMPTY_KEY;
+    }
+    int nclaim = 0;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        got[u] = -1;
+        if (kk[u] == EMPTY_KEY) continue;
+        const AccT val = s_vals[tid + u * G];
+        if (old[u] == EMPTY_KEY || old[u] == kk[u]) {
+            atomicAdd(&vals[home[u]], val);
+            if (old[u] == EMPTY_KEY) got[u] = home[u];
+        } else {
+            got[u] = table_add_claim<AccT>(keys, vals, mask, home[u], kk[u], val);
+        }
+        nclaim += got[u] >= 0;
+    }
+    // list the newly occupied slots: one global counter update per block
+    const int mine = nclaim ? atomicAdd(&s_claim[0], nclaim) : 0;
+    __syncthreads();
+    if (tid == 0) s_claim[1] = s_claim[0] ? atomicAdd(&a.hub_cnt[h], s_claim[0]) : 0;
+    __syncthreads();
+    if (nclaim) {
+        int32_t p = s_claim[1] + mine;
+#pragma unroll
+        for (int u = 0; u < PER; u++)
+            if (got[u] >= 0) slots[p++] = (int32_t)got[u];
     }
 }
 
-template <typename OffT, int WK, typename AccT, int MODE>
-__global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
-    constexpr int G = 1024;
-    __shared__ i128 s_k128[G / WAVE];
-    __shared__ i64 s_k64[G / WAVE];
-    __shared__ int32_t s_d[G / WAVE];
-    __shared__ i64 s_v[G / WAVE];
-    __shared__ i64 s_t[G / WAVE];
-    const OffT* off = (const OffT*)a.off;
-    const int32_t h = a.g_lo + blockIdx.x;
-    const int32_t v = a.hub_list[h];
-    const int tid = threadIdx.x;
-    if (!hub_queued(a, v)) {
-        if (tid == 0) {
-            a.gdec[h] = -1;
-            if constexpr (MODE == M_SYNC) a.sdec[v] = -1;
-        }
-        return;
-    }
-    const int64_t toff = a.hub_pre[h] - a.hub_pre[a.g_lo];
-    const int64_t cap = a.hub_pre[h + 1] - a.hub_pre[h];
-    int32_t* keys = a.hub_keys + toff;
-    AccT* vals = (AccT*)a.hub_vals + toff;
-    const int32_t* slots = a.hub_slots + toff / 2;
-    const int64_t nocc = a.hub_cnt[h];
+// Decision of a hub: the hub's occupied slots are split evenly over as many
+// blocks as it has insert chunks.  Each block scans its share (gathering
+// Sigma of every candidate) and clears it.  A hub with one block decides at
+// once; otherwise each block posts a partial best and k_hub_final, launched
+// next, combines them (the kernel boundary makes the partials visible on
+// every chiplet without fences inside the launch).
+template <int MODE, typename KeyT>
+__device__ __forceinline__ void hub_finish(const MoveArgs& a, int32_t h, int32_t v, i64 deg, const Best<KeyT>& b,
+                                           int lane) {
     const int32_t c = ld_c<MODE>(&a.Cp[v]);
     const i64 Ki = a.K[v];
     const int32_t gv = a.gid ? a.gid[v] : -1;
     const i64 Wv = gv >= 0 ? (i64)a.Wg[gv] : a.W;
-    Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, Wv, keys, vals, cap, tid, true, c, Ki, s_k64, s_d, s_v, s_t, slots, nocc)
-        : decide<G, MODE, i128, AccT>(a, Wv, keys, vals, cap, tid, true, c, Ki, s_k128, s_d, s_v, s_t, slots, nocc);
-    // clean the occupied slots for the next iteration
-    for (int64_t k = tid; k < nocc; k += G) {
-        const int32_t sl = slots[k];
-        keys[sl] = EMPTY_KEY;
-        vals[sl] = 0;
-    }
-    if (tid == 0) a.hub_cnt[h] = 0;
-    const i64 deg = (i64)off[v + 1] - (i64)off[v];
-    if (tid == 0) {
+    Decision dcs = finish_decision<MODE, KeyT>(a, Wv, true, c, Ki, b);
+    if (lane == 0) {
+        a.hub_cnt[h] = 0;
         if constexpr (MODE == M_SYNC) {
             a.sdec[v] = dcs.target;
         } else {
@@ -650,6 +699,108 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
         add_block_totals(a.ctl, a.bucket, 1, (u64)deg, (u64)dcs.nd, dcs.target >= 0 ? 1 : 0,
                          dcs.target >= 0 ? (u64)deg : 0, dcs.gain, (u64)dcs.positive);
     }
+}
+
+template <int MODE, typename KeyT, typename AccT, typename OffT>
+__device__ __forceinline__ void hub_decide_block(const MoveArgs& a, int32_t h, int32_t v, int64_t k, int64_t nch,
+                                                 KeyT* s_k, int32_t* s_d, i64* s_v, i64* s_t) {
+    constexpr int G = 1024;
+    const OffT* off = (const OffT*)a.off;
+    const int tid = threadIdx.x;
+    const int64_t toff = a.hub_pre[h] - a.hub_pre[a.tab_lo];
+    const int64_t cap = a.hub_pre[h + 1] - a.hub_pre[h];
+    int32_t* keys = a.hub_keys + toff;
+    AccT* vals = (AccT*)a.hub_vals + toff;
+    const int32_t* slots = a.hub_slots + toff / 2;
+    const int64_t nocc = a.hub_cnt[h];
+    const int64_t lo = nocc * k / nch, hi = nocc * (k + 1) / nch;
+    const int32_t c = ld_c<MODE>(&a.Cp[v]);
+    const i64 Ki = a.K[v];
+    const int32_t gv = a.gid ? a.gid[v] : -1;
+    const i64 Wv = gv >= 0 ? (i64)a.Wg[gv] : a.W;
+    const Best<KeyT> b = scan_table<G, MODE, KeyT, AccT>(a, Wv, keys, vals, cap, tid, c, Ki, s_k, s_d, s_v, s_t,
+                                                         slots + lo, hi - lo);
+    // clear this block's share of the table for the next iteration
+    for (int64_t x = lo + tid; x < hi; x += G) {
+        const int32_t sl = slots[x];
+        keys[sl] = EMPTY_KEY;
+        vals[sl] = 0;
+    }
+    if (nch == 1) {
+        hub_finish<MODE, KeyT>(a, h, v, (i64)off[v + 1] - (i64)off[v], b, tid);
+    } else if (tid == 0) {
+        HubPart* mine = a.hub_part + blockIdx.x;
+        const i128 key = (i128)b.bk;
+        mine->klo = (i64)(u64)key;
+        mine->khi = (i64)(key >> 64);
+        mine->v = b.bv;
+        mine->kic = b.kic;
+        mine->nd = b.nd;
+        mine->d = b.bd;
+    }
+}
+
+template <typename OffT, int WK, typename AccT, int MODE>
+__global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
+    constexpr int G = 1024;
+    __shared__ i128 s_k128[G / WAVE];
+    __shared__ i64 s_k64[G / WAVE];
+    __shared__ int32_t s_d[G / WAVE];
+    __shared__ i64 s_v[G / WAVE];
+    __shared__ i64 s_t[G / WAVE];
+    const int32_t ng = a.g_hi - a.g_lo;
+    const int64_t chunk_base = a.hch_pre[a.g_lo];
+    const int32_t h = a.g_lo + owner_of(a.hch_pre + a.g_lo, ng, chunk_base, blockIdx.x);
+    const int32_t v = a.hub_list[h];
+    const int64_t k = (int64_t)blockIdx.x - (a.hch_pre[h] - chunk_base);
+    const int64_t nch = a.hch_pre[h + 1] - a.hch_pre[h];
+    if (!hub_queued(a, v)) {
+        if (k == 0 && threadIdx.x == 0) {
+            a.gdec[h] = -1;
+            if constexpr (MODE == M_SYNC) a.sdec[v] = -1;
+        }
+        return;
+    }
+    if (!a.wide) hub_decide_block<MODE, i64, AccT, OffT>(a, h, v, k, nch, s_k64, s_d, s_v, s_t);
+    else hub_decide_block<MODE, i128, AccT, OffT>(a, h, v, k, nch, s_k128, s_d, s_v, s_t);
+}
+
+// Hubs of the launch with more than one decide block: one wave per hub
+// combines the partial bests (ties to the smaller community) and decides.
+template <int MODE, typename KeyT, typename OffT>
+__device__ __forceinline__ void hub_final_wave(const MoveArgs& a, int32_t h, int32_t v, int64_t nch,
+                                               const HubPart* parts, int lane) {
+    const OffT* off = (const OffT*)a.off;
+    KeyT bk = (sizeof(KeyT) == 8) ? (KeyT)INT64_MIN : (KeyT)(((i128)1) << 127);
+    int32_t bd = EMPTY_KEY;
+    i64 bv = 0, kic = 0, nd = 0;
+    for (int64_t x = lane; x < nch; x += WAVE) {
+        const HubPart& q = parts[x];
+        nd += q.nd;
+        kic = q.kic > kic ? q.kic : kic;
+        if (q.d == EMPTY_KEY) continue;
+        const KeyT key = (KeyT)(((i128)q.khi << 64) | (i128)(u64)q.klo);
+        if (bd == EMPTY_KEY || better(key, q.d, bk, bd)) { bk = key; bd = q.d; bv = q.v; }
+    }
+    if (bd == EMPTY_KEY) bk = (sizeof(KeyT) == 8) ? (KeyT)INT64_MIN : (KeyT)(((i128)1) << 127);
+    reduce_best<WAVE, KeyT>(bk, bd, bv, nullptr, nullptr, nullptr);
+    kic = reduce_max<WAVE>(kic, nullptr);
+    nd = reduce_sum<WAVE>(nd, nullptr);
+    hub_finish<MODE, KeyT>(a, h, v, (i64)off[v + 1] - (i64)off[v], Best<KeyT>{bk, bd, bd != EMPTY_KEY ? bv : 0, kic, nd},
+                           lane);
+}
+
+template <typename OffT, int MODE>
+__global__ void __launch_bounds__(256) k_hub_final(MoveArgs a) {
+    const int lane = threadIdx.x % WAVE;
+    const int32_t h = a.g_lo + (int32_t)((int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE);
+    if (h >= a.g_hi) return;  // uniform per wave
+    const int64_t nch = a.hch_pre[h + 1] - a.hch_pre[h];
+    const int32_t v = a.hub_list[h];
+    if (nch <= 1 || !hub_queued(a, v)) return;
+    const HubPart* parts = a.hub_part + (a.hch_pre[h] - a.hch_pre[a.g_lo]);
+    if (!a.wide) hub_final_wave<MODE, i64, OffT>(a, h, v, nch, parts, lane);
+    else hub_final_wave<MODE, i128, OffT>(a, h, v, nch, parts, lane);
 }
 
 template <typename OffT>
@@ -805,9 +956,9 @@ void launch_hub_insert(const LevelView& L, int mode, const MoveArgs& a, int64_t 
     });
 }
 
-void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s) {
-    const int32_t nh = a.g_hi - a.g_lo;
-    if (nh <= 0) return;
+void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s) {
+    const unsigned nh = (unsigned)nchunks;
+    if (nchunks <= 0) return;
     dispatch_types(L.t, [&](auto o, auto w, auto ac) {
         using OffT = typename decltype(o)::type;
         constexpr int WK = decltype(w)::value;
@@ -816,6 +967,21 @@ void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, hipStrea
         else if (mode == M_ASYNC_CACHED) k_hub_decide<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)nh, 1024, 0, s>>>(a);
         else k_hub_decide<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)nh, 1024, 0, s>>>(a);
     });
+}
+
+void launch_hub_final(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s) {
+    const int32_t nh = a.g_hi - a.g_lo;
+    if (nh <= 0) return;
+    const unsigned grid = (unsigned)((nh + 3) / 4);
+    if (L.t.off64) {
+        if (mode == M_SYNC) k_hub_final<int64_t, M_SYNC><<<grid, 256, 0, s>>>(a);
+        else if (mode == M_ASYNC_CACHED) k_hub_final<int64_t, M_ASYNC_CACHED><<<grid, 256, 0, s>>>(a);
+        else k_hub_final<int64_t, M_ASYNC_COHERENT><<<grid, 256, 0, s>>>(a);
+    } else {
+        if (mode == M_SYNC) k_hub_final<int32_t, M_SYNC><<<grid, 256, 0, s>>>(a);
+        else if (mode == M_ASYNC_CACHED) k_hub_final<int32_t, M_ASYNC_CACHED><<<grid, 256, 0, s>>>(a);
+        else k_hub_final<int32_t, M_ASYNC_COHERENT><<<grid, 256, 0, s>>>(a);
+    }
 }
 
 void launch_hub_mark(const LevelView& L, const MoveArgs& a, int64_t nchunks, hipStream_t s) {
