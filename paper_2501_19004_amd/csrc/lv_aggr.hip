@@ -314,15 +314,32 @@ __global__ void __launch_bounds__(1024) k_big_insert(Graph<OffT, WK> g, BigArgs 
         s_pre[tid] = pre;
         __syncthreads();
         const i64 total = s_pre[G - 1];
-        for (i64 f = tid; f < total; f += G) {
-            int lo = 0, hi = G - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_pre[mid] > f) hi = mid; else lo = mid + 1;
+        // U virtual arcs per round: their index loads, then their C' gathers, are issued together
+        constexpr int U = 4;
+        for (i64 fb = tid; fb < total; fb += U * G) {
+            i64 ee[U];
+            int32_t jj[U], dd[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const i64 f = fb + (i64)u * G;
+                ee[u] = -1;
+                if (f < total) {
+                    int lo = 0, hi = G - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] > f) hi = mid; else lo = mid + 1;
+                    }
+                    ee[u] = s_start[lo] + (f - (lo ? s_pre[lo - 1] : 0));
+                }
             }
-            const i64 e = s_start[lo] + (f - (lo ? s_pre[lo - 1] : 0));
-            const int32_t d = a.Cp[g.idx[e]];
-            table_add<AccT>(s_keys, s_vals, BIG_LCAP - 1, hash_slot<L2C>(d), d, (AccT)g.weight(e));
+#pragma unroll
+            for (int u = 0; u < U; u++) jj[u] = ee[u] >= 0 ? g.idx[ee[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < U; u++) dd[u] = ee[u] >= 0 ? a.Cp[jj[u]] : EMPTY_KEY;
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (ee[u] >= 0)
+                    table_add<AccT>(s_keys, s_vals, BIG_LCAP - 1, hash_slot<L2C>(dd[u]), dd[u], (AccT)g.weight(ee[u]));
         }
         __syncthreads();
     }
@@ -333,12 +350,47 @@ __global__ void __launch_bounds__(1024) k_big_insert(Graph<OffT, WK> g, BigArgs 
     int32_t* keys = a.keys + toff;
     AccT* vals = (AccT*)a.vals + toff;
     int32_t* slots = a.slots + toff / 2;  // cap >= 2 * distinct keys
-    for (int s = tid; s < BIG_LCAP; s += G) {
-        const int32_t d = s_keys[s];
-        if (d == EMPTY_KEY) continue;
-        const int64_t got = table_add_claim<AccT>(keys, vals, (uint32_t)(cap - 1), hash_slot_rt(d, log2cap), d,
-                                                  s_vals[s]);
-        if (got >= 0) slots[atomicAdd(&a.cnt[h], 1)] = (int32_t)got;
+    // the first probes of all of this thread's keys are issued together; a
+    // key whose home slot holds another key continues along its probe sequence
+    constexpr int PER = BIG_LCAP / G;
+    const uint32_t mask = (uint32_t)(cap - 1);
+    int32_t kk[PER], old[PER];
+    uint32_t home[PER];
+    int64_t got[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) kk[u] = s_keys[tid + u * G];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        home[u] = kk[u] != EMPTY_KEY ? hash_slot_rt(kk[u], log2cap) : 0u;
+        old[u] = kk[u] != EMPTY_KEY ? atomicCAS(&keys[home[u]], EMPTY_KEY, kk[u]) : EMPTY_KEY;
+    }
+    int nclaim = 0;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        got[u] = -1;
+        if (kk[u] == EMPTY_KEY) continue;
+        const AccT val = s_vals[tid + u * G];
+        if (old[u] == EMPTY_KEY || old[u] == kk[u]) {
+            atomicAdd(&vals[home[u]], val);
+            if (old[u] == EMPTY_KEY) got[u] = home[u];
+        } else {
+            got[u] = table_add_claim<AccT>(keys, vals, mask, home[u], kk[u], val);
+        }
+        nclaim += got[u] >= 0;
+    }
+    // list the newly occupied slots: one global counter update per block
+    __shared__ int32_t s_claim[2];
+    if (tid == 0) s_claim[0] = 0;
+    __syncthreads();
+    const int mine = nclaim ? atomicAdd(&s_claim[0], nclaim) : 0;
+    __syncthreads();
+    if (tid == 0) s_claim[1] = s_claim[0] ? atomicAdd(&a.cnt[h], s_claim[0]) : 0;
+    __syncthreads();
+    if (nclaim) {
+        int32_t p = s_claim[1] + mine;
+#pragma unroll
+        for (int u = 0; u < PER; u++)
+            if (got[u] >= 0) slots[p++] = (int32_t)got[u];
     }
 }
 

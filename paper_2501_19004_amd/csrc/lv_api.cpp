@@ -311,7 +311,8 @@ struct IterTotals {
 IterTotals sum_iter(const Ctl& c) {
     IterTotals t{};
     for (int k = 0; k < STRIPES; k++) {
-        t.S += ((unsigned __int128)c.s_hi[k] << 64) + (unsigned __int128)c.s_lo[k];
+        t.S += ((unsigned __int128)c.s_hi[k] << 64) + ((unsigned __int128)c.s_mid[k] << 32) +
+               (unsigned __int128)c.s_lo[k];
         t.moves += c.moves[k];
         t.positive += c.positive[k];
     }
@@ -665,7 +666,7 @@ louvain_status Runner::run() {
         const int NBT = NB_MOVE + 1;  // LDS buckets + hub
         int32_t bcount[MAX_BUCKETS] = {};
         timed(H, K_PASS_INIT, 0, [&] {
-            launch_classify(L, H->mb, vb, Cp, K, Sig, s);
+            launch_classify(L, H->mb, vb, Cp, K, Sig, ctl(), s);
             bucketize_vertices(n, vb, nullptr, 0, nullptr, nullptr, blkcnt, blkoff, blist, ctl()->bcount, scan, s);
         });
         if ((st = readback(H, bcount, ctl()->bcount, NBT * sizeof(int32_t))) != LOUVAIN_OK) return st;
@@ -673,10 +674,11 @@ louvain_status Runner::run() {
         segs[0] = 0;
         for (int b = 0; b < NBT; b++) segs[b + 1] = segs[b] + bcount[b];
         const int64_t nonisolated = segs[NBT];
-        timed(H, K_PASS_INIT, 0, [&] {
-            for (int b = 0; b < NBT; b++)
-                launch_rowsum(L, b, blist + segs[b], bcount[b], K, Sig, ctl(), s);
-        });
+        if (L.t.wk != 0)  // unit weights: the row sums are the degrees, written by the classification
+            timed(H, K_PASS_INIT, 0, [&] {
+                for (int b = 0; b < NBT; b++)
+                    launch_rowsum(L, b, blist + segs[b], bcount[b], K, Sig, ctl(), s);
+            });
         // hub tables and insert chunks over the static hub list (ascending vertex id)
         const int32_t nhub = bcount[NB_MOVE];
         const int32_t* hub_list = blist + segs[NB_MOVE];

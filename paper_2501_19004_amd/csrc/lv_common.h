@@ -32,7 +32,11 @@ struct Ctl {
     // ---- zeroed before every local-moving iteration
     int32_t qcount[MAX_BUCKETS];  // next-iteration queue sizes, per move bucket
     int32_t pad0[2];
-    u64 s_lo[STRIPES];            // 128-bit sums of applied gains (two's complement)
+    // sums of applied gains, split so that every part is added without a
+    // returning atomic: gain = hi * 2^64 + mid * 2^32 + lo with lo, mid in
+    // [0, 2^32); the host adds the parts modulo 2^128
+    u64 s_lo[STRIPES];
+    u64 s_mid[STRIPES];
     u64 s_hi[STRIPES];
     u64 moves[STRIPES];           // moves applied
     u64 positive[STRIPES];        // evaluated vertices whose best gain was positive (before Pick-Less)
@@ -176,6 +180,16 @@ __device__ __forceinline__ void atomic_add_i128(u64* lo, u64* hi, i128 v) {
     u64 old = atomicAdd(lo, vlo);
     vhi += (old + vlo < old) ? 1ull : 0ull;
     if (vhi) atomicAdd(hi, vhi);
+}
+
+// Parts of a 128-bit value for split accumulation (lo and mid < 2^32, so
+// sums of up to 2^32 parts cannot overflow; hi wraps modulo 2^64, which is
+// exact modulo 2^128 once recombined).
+struct Split128 {
+    u64 lo, mid, hi;
+};
+__device__ __forceinline__ Split128 split128(i128 v) {
+    return Split128{(u64)v & 0xffffffffull, (u64)(v >> 32) & 0xffffffffull, (u64)(v >> 64)};
 }
 
 // Barrier for a group of G threads (G <= 64: inside one wave).

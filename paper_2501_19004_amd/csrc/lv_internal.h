@@ -156,7 +156,7 @@ void iota_i32(int32_t* p, int64_t n, hipStream_t s);
 
 // ---- launchers: pass init and local moving (lv_move.hip)
 void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int32_t* Cp, i64* K, i64* Sig,
-                     hipStream_t s);
+                     Ctl* ctl, hipStream_t s);
 // Ordered partition of the level's vertices into NB_MOVE+1 bucket segments
 // (all vertices with arcs, or the flagged ones when use_flags); bucket totals
 // go to totals[0..NB_MOVE].  blkcnt/blkoff: (NB_MOVE+1) * bucket_blocks(n) (+1).

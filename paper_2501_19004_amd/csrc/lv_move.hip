@@ -120,23 +120,35 @@ __device__ __forceinline__ int32_t group_bcast(int32_t v, int32_t* s_x) {
 }
 
 // ------------------------------------------------------------ pass init
-template <typename OffT>
+// Degree bucket of every vertex; C' = identity.  K' = Sigma' = 0, to be
+// filled by the row sums -- except for unit weights (UNIT), where the row
+// sum is the degree and is written here together with its maximum.
+template <typename OffT, bool UNIT>
 __global__ void __launch_bounds__(256) k_classify(const OffT* __restrict__ off, int64_t n, Buckets B,
                                                   uint8_t* __restrict__ vbucket, int32_t* __restrict__ Cp,
-                                                  i64* __restrict__ K, i64* __restrict__ Sig) {
+                                                  i64* __restrict__ K, i64* __restrict__ Sig, Ctl* ctl) {
+    __shared__ u64 s_max;
+    if (UNIT && threadIdx.x == 0) s_max = 0;
+    if (UNIT) __syncthreads();
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int b = 255;
-    const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
-    if (deg > 0) {
-        b = B.nb;
-        for (int k = 0; k < B.nb; k++)
-            if (deg <= B.maxdeg[k]) { b = k; break; }
+    if (v < n) {
+        int b = 255;
+        const int64_t deg = (int64_t)off[v + 1] - (int64_t)off[v];
+        if (deg > 0) {
+            b = B.nb;
+            for (int k = 0; k < B.nb; k++)
+                if (deg <= B.maxdeg[k]) { b = k; break; }
+        }
+        vbucket[v] = (uint8_t)b;
+        Cp[v] = (int32_t)v;
+        K[v] = UNIT ? deg : 0;
+        Sig[v] = UNIT ? deg : 0;
+        if (UNIT && deg > 0) atomicMax(&s_max, (u64)deg);
     }
-    vbucket[v] = (uint8_t)b;
-    Cp[v] = (int32_t)v;
-    K[v] = 0;
-    Sig[v] = 0;
+    if (UNIT) {
+        __syncthreads();
+        if (threadIdx.x == 0 && s_max) atomicMax(&ctl->kmax, s_max);
+    }
 }
 
 struct VBucket {
@@ -293,10 +305,9 @@ __device__ __forceinline__ Best<KeyT> scan_table(const MoveArgs& a, i64 W, const
 // against staying, Pick-Less, and (concurrent modes) the minimum-label rule.
 template <int MODE, typename KeyT>
 __device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bool active, int32_t c, i64 Ki,
-                                                    const Best<KeyT>& b) {
+                                                    const Best<KeyT>& b, i64 Sc) {
     Decision r{-1, 0, b.kic, 0, b.nd, b.bd != EMPTY_KEY ? b.bv : 0, 0};
     if (active && b.bd != EMPTY_KEY) {
-        const i64 Sc = ld_s<MODE>(&a.Sig[c]);
         const KeyT stay = (KeyT)W * b.kic - (KeyT)Ki * (Sc - Ki);
         const KeyT gk = b.bk - stay;
         r.positive = gk > 0;
@@ -312,15 +323,14 @@ __device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bo
     return r;
 }
 
-// Per-group decision after the table is filled.
+// Per-group decision after the table is filled (Sc: Sigma of c as read).
 template <int G, int MODE, typename KeyT, typename AccT>
 __device__ __forceinline__ Decision decide(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals, int64_t cap,
-                                           int lane, bool active, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
-                                           i64* s_v, i64* s_t, const int32_t* list = nullptr,
-                                           int64_t nlist = 0) {
+                                           int lane, bool active, int32_t c, i64 Ki, i64 Sc, KeyT* s_k, int32_t* s_d,
+                                           i64* s_v, i64* s_t) {
     const Best<KeyT> b = scan_table<G, MODE, KeyT, AccT>(a, W, keys, vals, cap, lane, c, Ki, s_k, s_d, s_v, s_t,
-                                                         list, nlist);
-    return finish_decision<MODE, KeyT>(a, W, active, c, Ki, b);
+                                                         nullptr, 0);
+    return finish_decision<MODE, KeyT>(a, W, active, c, Ki, b, Sc);
 }
 
 // ASYNC move with validation: Sigma of the target is updated by an atomic
@@ -366,8 +376,10 @@ __device__ __forceinline__ void note_evaluation(const MoveArgs& a, int32_t i, co
     a.f_adv[i] = d.bestk - d.kic;
 }
 
-__device__ __forceinline__ void add_block_totals(Ctl* ctl, int bucket, u64 ne, u64 na, u64 nd, u64 nm, u64 nma,
-                                                 i128 gain, u64 npos) {
+// Block totals into the striped counters; no atomic here waits for its
+// result, so the block retires as soon as they are issued.
+__device__ __forceinline__ void add_block_totals_split(Ctl* ctl, int bucket, u64 ne, u64 na, u64 nd, u64 nm, u64 nma,
+                                                       const Split128& gain, u64 npos) {
     const int st = blockIdx.x & (STRIPES - 1);
     if (!ne) return;
     if (npos) atomicAdd(&ctl->positive[st], npos);
@@ -375,11 +387,17 @@ __device__ __forceinline__ void add_block_totals(Ctl* ctl, int bucket, u64 ne, u
     atomicAdd(&ctl->bstat[1][bucket][st], na);
     atomicAdd(&ctl->bstat[2][bucket][st], nd);
     if (nm) {
-        atomic_add_i128(&ctl->s_lo[st], &ctl->s_hi[st], gain);
+        if (gain.lo) atomicAdd(&ctl->s_lo[st], gain.lo);
+        if (gain.mid) atomicAdd(&ctl->s_mid[st], gain.mid);
+        if (gain.hi) atomicAdd(&ctl->s_hi[st], gain.hi);
         atomicAdd(&ctl->moves[st], nm);
         atomicAdd(&ctl->bstat[3][bucket][st], nm);
         atomicAdd(&ctl->bstat[4][bucket][st], nma);
     }
+}
+__device__ __forceinline__ void add_block_totals(Ctl* ctl, int bucket, u64 ne, u64 na, u64 nd, u64 nm, u64 nma,
+                                                 i128 gain, u64 npos) {
+    add_block_totals_split(ctl, bucket, ne, na, nd, nm, nma, split128(gain), npos);
 }
 
 // Block-level scratch shared by every local-moving path (sized for the
@@ -433,15 +451,21 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     group_sync<G>();
 
     int32_t c = 0;
-    i64 Ki = 0, o0 = 0, o1 = 0;
+    i64 Ki = 0, o0 = 0, o1 = 0, Sc = 0;
     if (active) {
         c = ld_c<MODE>(&a.Cp[i]);
         Ki = a.K[i];
         o0 = (i64)g.off[i];
         o1 = (i64)g.off[i + 1];
+        Sc = ld_s<MODE>(&a.Sig[c]);  // in flight while the row is read
     }
-    // U arcs per round: their index loads, then their C' gathers, are issued together.
+    // U arcs per round: their index loads, then their C' gathers, are issued
+    // together.  The first round's neighbours stay in registers: when the row
+    // fits in one round they are flagged from there if the vertex moves.
     constexpr int U = 4;
+    int32_t j0[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) j0[u] = i;
     for (i64 e0 = o0 + lane; e0 < o1; e0 += U * G) {
         int32_t jj[U], dd[U];
         AccT ww[U];
@@ -450,6 +474,10 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
             const i64 e = e0 + (i64)u * G;
             jj[u] = e < o1 ? g.idx[e] : i;
             ww[u] = e < o1 ? (AccT)g.weight(e) : (AccT)0;
+        }
+        if (e0 == o0 + lane) {
+#pragma unroll
+            for (int u = 0; u < U; u++) j0[u] = jj[u];
         }
 #pragma unroll
         for (int u = 0; u < U; u++) dd[u] = jj[u] != i ? ld_c<MODE>(&a.Cp[jj[u]]) : EMPTY_KEY;
@@ -460,8 +488,8 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     group_sync<G>();
 
     Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, sh.k64, sh.d, sh.v, sh.t)
-        : decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, sh.k128, sh.d, sh.v, sh.t);
+        ? decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k64, sh.d, sh.v, sh.t)
+        : decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k128, sh.d, sh.v, sh.t);
 
     if (a.learn && active && lane == 0) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
@@ -470,7 +498,14 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
         int32_t t = -1;
         if (lane == 0 && dcs.target >= 0 && apply_async<MODE>(a, Wi, i, c, Ki, dcs)) t = dcs.target;
         t = group_bcast<G>(t, sh.x);
-        if ((a.prune || a.learn) && t >= 0) mark_neighbours<G>(a, g, i, o0, o1, lane);
+        if ((a.prune || a.learn) && t >= 0) {
+            if (o1 - o0 <= (i64)U * G) {
+#pragma unroll
+                for (int u = 0; u < U; u++) mark_one(a, i, j0[u]);
+            } else {
+                mark_neighbours<G>(a, g, i, o0, o1, lane);
+            }
+        }
     }
     if (lane == 0) {
         sh.gain[grp] = dcs.gain;
@@ -481,7 +516,38 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
         sh.nd[grp] = dcs.nd;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (!a.Sg) {
+        // block totals: wave 0 reduces the NG group results in parallel
+        if (threadIdx.x < WAVE) {
+            const int k = threadIdx.x;
+            i64 ne = 0, na = 0, ndt = 0, nm = 0, nma = 0, np = 0;
+            Split128 sp{0, 0, 0};
+            if (k < NG && sh.arcs[k] >= 0) {
+                ne = 1;
+                na = sh.arcs[k];
+                ndt = sh.nd[k];
+                np = sh.pos[k];
+                if (sh.dec[k] >= 0) {
+                    nm = 1;
+                    nma = sh.arcs[k];
+                    sp = split128(sh.gain[k]);
+                }
+            }
+            if constexpr (NG > 1) {
+                ne = group_sum64<WAVE>(ne);
+                na = group_sum64<WAVE>(na);
+                ndt = group_sum64<WAVE>(ndt);
+                nm = group_sum64<WAVE>(nm);
+                nma = group_sum64<WAVE>(nma);
+                np = group_sum64<WAVE>(np);
+                sp.lo = (u64)group_sum64<WAVE>((i64)sp.lo);
+                sp.mid = (u64)group_sum64<WAVE>((i64)sp.mid);
+                sp.hi = (u64)group_sum64<WAVE>((i64)sp.hi);
+            }
+            if (k == 0)
+                add_block_totals_split(a.ctl, bucket, (u64)ne, (u64)na, (u64)ndt, (u64)nm, (u64)nma, sp, (u64)np);
+        }
+    } else if (threadIdx.x == 0) {
         i128 sg = 0;
         u64 nm = 0, ne = 0, na = 0, ndt = 0, nma = 0, np = 0;
         for (int k = 0; k < NG; k++) {
@@ -493,21 +559,19 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
             if (sh.dec[k] >= 0) { sg += sh.gain[k]; nm++; nma += (u64)sh.arcs[k]; }
         }
         add_block_totals(a.ctl, bucket, ne, na, ndt, nm, nma, sg, np);
-        if (a.Sg) {
-            // per-graph gain sums, one 128-bit atomic per run of equal graph id
-            int32_t cur = -1;
-            i128 acc = 0;
-            for (int k = 0; k < NG; k++) {
-                if (sh.arcs[k] < 0 || sh.dec[k] < 0) continue;
-                if (sh.gi[k] != cur) {
-                    if (cur >= 0 && acc != 0) atomic_add_i128(&a.Sg[2 * cur], &a.Sg[2 * cur + 1], acc);
-                    cur = sh.gi[k];
-                    acc = 0;
-                }
-                acc += sh.gain[k];
+        // per-graph gain sums, one 128-bit atomic per run of equal graph id
+        int32_t cur = -1;
+        i128 acc = 0;
+        for (int k = 0; k < NG; k++) {
+            if (sh.arcs[k] < 0 || sh.dec[k] < 0) continue;
+            if (sh.gi[k] != cur) {
+                if (cur >= 0 && acc != 0) atomic_add_i128(&a.Sg[2 * cur], &a.Sg[2 * cur + 1], acc);
+                cur = sh.gi[k];
+                acc = 0;
             }
-            if (cur >= 0 && acc != 0) atomic_add_i128(&a.Sg[2 * cur], &a.Sg[2 * cur + 1], acc);
+            acc += sh.gain[k];
         }
+        if (cur >= 0 && acc != 0) atomic_add_i128(&a.Sg[2 * cur], &a.Sg[2 * cur + 1], acc);
     }
 }
 
@@ -685,7 +749,7 @@ __device__ __forceinline__ void hub_finish(const MoveArgs& a, int32_t h, int32_t
     const i64 Ki = a.K[v];
     const int32_t gv = a.gid ? a.gid[v] : -1;
     const i64 Wv = gv >= 0 ? (i64)a.Wg[gv] : a.W;
-    Decision dcs = finish_decision<MODE, KeyT>(a, Wv, true, c, Ki, b);
+    Decision dcs = finish_decision<MODE, KeyT>(a, Wv, true, c, Ki, b, ld_s<MODE>(&a.Sig[c]));
     if (lane == 0) {
         a.hub_cnt[h] = 0;
         if constexpr (MODE == M_SYNC) {
@@ -852,12 +916,17 @@ __global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a, const int32_t* _
 }  // namespace
 
 void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int32_t* Cp, i64* K, i64* Sig,
-                     hipStream_t s) {
+                     Ctl* ctl, hipStream_t s) {
     if (L.n <= 0) return;
-    if (L.t.off64)
-        k_classify<int64_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int64_t*)L.off, L.n, B, vbucket, Cp, K, Sig);
-    else
-        k_classify<int32_t><<<blocks_for(L.n, 256), 256, 0, s>>>((const int32_t*)L.off, L.n, B, vbucket, Cp, K, Sig);
+    const unsigned grid = blocks_for(L.n, 256);
+    const bool unit = L.t.wk == 0;
+    if (L.t.off64) {
+        if (unit) k_classify<int64_t, true><<<grid, 256, 0, s>>>((const int64_t*)L.off, L.n, B, vbucket, Cp, K, Sig, ctl);
+        else k_classify<int64_t, false><<<grid, 256, 0, s>>>((const int64_t*)L.off, L.n, B, vbucket, Cp, K, Sig, ctl);
+    } else {
+        if (unit) k_classify<int32_t, true><<<grid, 256, 0, s>>>((const int32_t*)L.off, L.n, B, vbucket, Cp, K, Sig, ctl);
+        else k_classify<int32_t, false><<<grid, 256, 0, s>>>((const int32_t*)L.off, L.n, B, vbucket, Cp, K, Sig, ctl);
+    }
 }
 
 void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags, const int32_t* gid,
@@ -934,13 +1003,8 @@ void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, co
                 k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_CACHED><<<grid, BLOCK, 0, s>>>(a, list, count);
             else k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_COHERENT><<<grid, BLOCK, 0, s>>>(a, list, count);
         };
-        switch (bucket) {
-            case 0: go(IntTag<0>{}); break;
-            case 1: go(IntTag<1>{}); break;
-            case 2: go(IntTag<2>{}); break;
-            case 3: go(IntTag<3>{}); break;
-            default: go(IntTag<4>{}); break;
-        }
+        // buckets 0-3 run in k_move_fused; only the workgroup bucket has its own launch
+        if (bucket == 4) go(IntTag<4>{});
     });
 }
 
