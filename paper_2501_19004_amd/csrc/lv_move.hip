@@ -172,6 +172,7 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_rowsum(Graph<OffT, WK> g,
                                                               i64* __restrict__ Sig, Ctl* ctl) {
     constexpr int BLOCK = G > 256 ? G : 256;
     constexpr int NG = BLOCK / G;
+    static_assert(G <= WAVE || G == BLOCK, "a group is at most one wave or the whole workgroup");
     __shared__ i64 s_t[BLOCK / WAVE];
     __shared__ u64 s_max;
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
@@ -424,6 +425,10 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     constexpr int BLOCK = G > 256 ? G : 256;
     constexpr int NG = BLOCK / G;
     constexpr int L2C = Log2<CAP>::v;
+    // group reductions work inside one wave or over the whole workgroup, and
+    // the per-group slots of MoveShm hold 32 groups
+    static_assert(G <= WAVE || G == BLOCK, "a group is at most one wave or the whole workgroup");
+    static_assert(NG <= 32, "MoveShm holds 32 groups per block");
     const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t slot = blk * NG + grp;
