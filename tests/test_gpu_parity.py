@@ -259,3 +259,36 @@ def test_full_size_sync_first_iteration_sampled(rmat22):
         expect = d if (d is not None and gain > 0) else int(i)
         assert cp[i] == expect, (int(i), int(deg[i]), int(cp[i]), expect)
     assert int(first["sig"].sum()) == W
+
+
+@pytest.fixture(scope="module")
+def grid4096():
+    g = gg.grid(4096, 4096, seed=4096)
+    g.weights = g.weights.astype(np.int64)
+    return g
+
+
+def test_full_size_sync_grid4096(grid4096):
+    """The road-like 4096x4096 grid (16.8M vertices, 60.7M arcs, weights 1-16)
+    at full size in SYNC mode: the final membership, pass and iteration counts
+    and the exact modularity equal the oracle's SYNC run."""
+    g = grid4096
+    print("[case] grid 4096x4096 SYNC full run", flush=True)
+    memb, (q, num, den), _, _, st = run_gpu(g, lv.SYNC, trace=False)
+    ref = oracle.louvain(g, oracle.Params(mode=oracle.SYNC))
+    assert (st.passes, st.iterations) == (ref.passes, ref.iterations)
+    assert np.array_equal(memb, ref.membership)
+    assert (num, den) == oracle.modularity_parts(g, ref.membership)
+
+
+def test_full_size_async_grid4096(grid4096):
+    """The same grid in ASYNC mode: exact modularity of the GPU membership,
+    dense ids, Q within 0.002 of the sequential oracle's (one-sided)."""
+    g = grid4096
+    print("[case] grid 4096x4096 ASYNC full run", flush=True)
+    memb, (q, num, den), _, _, st = run_gpu(g, lv.ASYNC, trace=False)
+    assert (num, den) == oracle.modularity_parts(g, memb)
+    assert memb.min() == 0 and memb.max() == st.communities - 1
+    qo = oracle.modularity(g, oracle.louvain(g).membership)
+    print(f"Q_gpu - Q_oracle = {q - qo:+.5f}")
+    assert q >= qo - 0.002, (q, qo)
