@@ -258,10 +258,10 @@ struct Best {
 
 // Scans the table slots owned by this lane (all cap slots, or the nlist slots
 // listed in `list`) and reduces over the group; every lane returns the same.
-template <int G, int MODE, typename KeyT, typename AccT>
+template <int G, int MODE, typename KeyT, typename AccT, typename ListT = int32_t>
 __device__ __forceinline__ Best<KeyT> scan_table(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals,
                                                  int64_t cap, int lane, int32_t c, i64 Ki, KeyT* s_k, int32_t* s_d,
-                                                 i64* s_v, i64* s_t, const int32_t* list, int64_t nlist) {
+                                                 i64* s_v, i64* s_t, const ListT* list, int64_t nlist) {
     KeyT bk = 0;
     int32_t bd = EMPTY_KEY;
     i64 bv = 0, kic = 0, nd = 0;
@@ -324,13 +324,14 @@ __device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bo
     return r;
 }
 
-// Per-group decision after the table is filled (Sc: Sigma of c as read).
+// Per-group decision after the table is filled (Sc: Sigma of c as read);
+// list/nlist: the table's occupied slots.
 template <int G, int MODE, typename KeyT, typename AccT>
 __device__ __forceinline__ Decision decide(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals, int64_t cap,
                                            int lane, bool active, int32_t c, i64 Ki, i64 Sc, KeyT* s_k, int32_t* s_d,
-                                           i64* s_v, i64* s_t) {
-    const Best<KeyT> b = scan_table<G, MODE, KeyT, AccT>(a, W, keys, vals, cap, lane, c, Ki, s_k, s_d, s_v, s_t,
-                                                         nullptr, 0);
+                                           i64* s_v, i64* s_t, const uint16_t* list, int64_t nlist) {
+    const Best<KeyT> b = scan_table<G, MODE, KeyT, AccT, uint16_t>(a, W, keys, vals, cap, lane, c, Ki, s_k, s_d, s_v,
+                                                                   s_t, list, nlist);
     return finish_decision<MODE, KeyT>(a, W, active, c, Ki, b, Sc);
 }
 
@@ -414,6 +415,7 @@ struct MoveShm {
     int32_t dec[32];
     int32_t pos[32];
     int32_t gi[32];
+    int32_t ncl[32];  // occupied slots listed per group
     i64 arcs[32], nd[32];
 };
 
@@ -421,7 +423,8 @@ struct MoveShm {
 // lanes with a CAP-slot table in LDS (keys/vals point at this block's LDS).
 template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE>
 __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __restrict__ list, int32_t count,
-                                           int64_t blk, int bucket, int32_t* s_keys, AccT* s_vals, MoveShm& sh) {
+                                           int64_t blk, int bucket, int32_t* s_keys, AccT* s_vals, uint16_t* s_list,
+                                           MoveShm& sh) {
     constexpr int BLOCK = G > 256 ? G : 256;
     constexpr int NG = BLOCK / G;
     constexpr int L2C = Log2<CAP>::v;
@@ -429,6 +432,7 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     // the per-group slots of MoveShm hold 32 groups
     static_assert(G <= WAVE || G == BLOCK, "a group is at most one wave or the whole workgroup");
     static_assert(NG <= 32, "MoveShm holds 32 groups per block");
+    static_assert(CAP <= 65536, "slot lists hold 16-bit slot numbers");
     const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t slot = blk * NG + grp;
@@ -452,7 +456,9 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     const i64 Wi = gi >= 0 ? (i64)a.Wg[gi] : a.W;
     int32_t* keys = s_keys + grp * CAP;
     AccT* vals = s_vals + grp * CAP;
+    uint16_t* occ = s_list + grp * (CAP / 2);  // distinct keys <= degree <= CAP / 2
     for (int s = lane; s < CAP; s += G) { keys[s] = EMPTY_KEY; vals[s] = 0; }
+    if (lane == 0) sh.ncl[grp] = 0;
     group_sync<G>();
 
     int32_t c = 0;
@@ -487,14 +493,20 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
 #pragma unroll
         for (int u = 0; u < U; u++) dd[u] = jj[u] != i ? ld_c<MODE>(&a.Cp[jj[u]]) : EMPTY_KEY;
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            if (dd[u] != EMPTY_KEY) table_add<AccT>(keys, vals, CAP - 1, hash_slot<L2C>(dd[u]), dd[u], ww[u]);
+        for (int u = 0; u < U; u++) {
+            if (dd[u] == EMPTY_KEY) continue;
+            const int64_t got = table_add_claim<AccT>(keys, vals, CAP - 1, hash_slot<L2C>(dd[u]), dd[u], ww[u]);
+            if (got >= 0) occ[atomicAdd(&sh.ncl[grp], 1)] = (uint16_t)got;
+        }
     }
     group_sync<G>();
+    const int32_t nocc = sh.ncl[grp];
 
     Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k64, sh.d, sh.v, sh.t)
-        : decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k128, sh.d, sh.v, sh.t);
+        ? decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k64, sh.d, sh.v, sh.t, occ,
+                                     nocc)
+        : decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k128, sh.d, sh.v, sh.t,
+                                      occ, nocc);
 
     if (a.learn && active && lane == 0) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
@@ -586,8 +598,9 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
     constexpr int NG = (G > 256 ? G : 256) / G;
     __shared__ int32_t s_keys[NG * CAP];
     __shared__ AccT s_vals[NG * CAP];
+    __shared__ uint16_t s_list[NG * CAP / 2];
     __shared__ MoveShm sh;
-    move_block<OffT, WK, AccT, G, CAP, MODE>(a, list, count, blockIdx.x, a.bucket, s_keys, s_vals, sh);
+    move_block<OffT, WK, AccT, G, CAP, MODE>(a, list, count, blockIdx.x, a.bucket, s_keys, s_vals, s_list, sh);
 }
 
 // Buckets 0..3 (all 256-thread blocks) in one launch: block ranges
@@ -608,26 +621,34 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
     switch (bk) {
         case 0: {
             constexpr int NG = 256 / MOVE_G[0];
+            constexpr int TB = NG * MOVE_CAP[0];
             move_block<OffT, WK, AccT, MOVE_G[0], MOVE_CAP[0], MODE>(
-                aa, f.list[0], f.count[0], blk, 0, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[0] * 4), sh);
+                aa, f.list[0], f.count[0], blk, 0, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
+                (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
         }
         case 1: {
             constexpr int NG = 256 / MOVE_G[1];
+            constexpr int TB = NG * MOVE_CAP[1];
             move_block<OffT, WK, AccT, MOVE_G[1], MOVE_CAP[1], MODE>(
-                aa, f.list[1], f.count[1], blk, 1, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[1] * 4), sh);
+                aa, f.list[1], f.count[1], blk, 1, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
+                (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
         }
         case 2: {
             constexpr int NG = 256 / MOVE_G[2];
+            constexpr int TB = NG * MOVE_CAP[2];
             move_block<OffT, WK, AccT, MOVE_G[2], MOVE_CAP[2], MODE>(
-                aa, f.list[2], f.count[2], blk, 2, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[2] * 4), sh);
+                aa, f.list[2], f.count[2], blk, 2, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
+                (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
         }
         default: {
             constexpr int NG = 256 / MOVE_G[3];
+            constexpr int TB = NG * MOVE_CAP[3];
             move_block<OffT, WK, AccT, MOVE_G[3], MOVE_CAP[3], MODE>(
-                aa, f.list[3], f.count[3], blk, 3, (int32_t*)dyn, (AccT*)(dyn + NG * MOVE_CAP[3] * 4), sh);
+                aa, f.list[3], f.count[3], blk, 3, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
+                (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
         }
     }
@@ -1068,7 +1089,7 @@ void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const Fu
         using AccT = typename decltype(ac)::type;
         size_t shm = 0;
         for (int b = 0; b < 4; b++)
-            shm = std::max(shm, (size_t)(256 / MOVE_G[b]) * MOVE_CAP[b] * (4 + sizeof(AccT)));
+            shm = std::max(shm, (size_t)(256 / MOVE_G[b]) * MOVE_CAP[b] * (4 + sizeof(AccT) + 1));
         if (mode == M_SYNC) k_move_fused<OffT, WK, AccT, M_SYNC><<<(unsigned)grid, 256, shm, s>>>(a, f);
         else if (mode == M_ASYNC_CACHED) k_move_fused<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)grid, 256, shm, s>>>(a, f);
         else k_move_fused<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)grid, 256, shm, s>>>(a, f);
