@@ -48,7 +48,7 @@ struct Layout {
     size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots, hpart;
     int64_t part_cap;
     // batched runs (count graphs; absent for a single graph)
-    size_t gid[2], gid0, Wg, gact, Sg, gcnt, cmin, vbase, gq, segcnt, segstart, prefall;
+    size_t gid[2], gid0, Wg, gact, Sg, Pg, gcnt, cmin, vbase, gq, segcnt, segstart, prefall;
     int64_t bitmap_words;
     int64_t pool_entries;
     size_t total;
@@ -110,6 +110,7 @@ bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
         L->Wg = take(G * 8);
         L->gact = take(G);
         L->Sg = take(G * 16);
+        L->Pg = take(G * 8);      // per graph: evaluations with a positive best gain
         L->gcnt = take(G * 16);   // per graph: vertices with arcs, used communities
         L->cmin = take(G * 4);
         L->vbase = take((G + 1) * 8);
@@ -401,8 +402,8 @@ louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t
             return fail(nullptr, LOUVAIN_ERR_INVALID, "vbase must start at 0 and end at n");
         for (int64_t k = 0; k < count; k++)
             if (vbase[k + 1] < vbase[k]) return fail(nullptr, LOUVAIN_ERR_INVALID, "vbase must be non-decreasing");
-        if (p->pruner == LOUVAIN_PRUNE_LEARNED)
-            return fail(nullptr, LOUVAIN_ERR_INVALID, "batched runs support pruner NONE and FLAGS");
+        if (p->pruner == LOUVAIN_PRUNE_LEARNED && p->mode == LOUVAIN_SYNC)
+            return fail(nullptr, LOUVAIN_ERR_INVALID, "batched runs support the learned pruner in ASYNC mode only");
     }
     Layout lay;
     make_layout(g->n, g->nnz, count, p->async_slices, &lay);
@@ -622,11 +623,12 @@ louvain_status Runner::run() {
     uint8_t* gact_dev = batch ? at<uint8_t>(Y.gact) : nullptr;
     u64* Wg_dev = batch ? at<u64>(Y.Wg) : nullptr;
     u64* Sg_dev = batch ? at<u64>(Y.Sg) : nullptr;
+    u64* Pg_dev = batch && learned ? at<u64>(Y.Pg) : nullptr;
     u64* gcnt_dev = batch ? at<u64>(Y.gcnt) : nullptr;
     std::vector<uint8_t> alive(nbg, 1), act(nbg, 0), ran(nbg, 0);
     std::vector<int32_t> li_g(nbg, 0);
     std::vector<int64_t> nver(nbg, 0);
-    std::vector<u64> hS(2 * nbg), hcnt(2 * nbg);
+    std::vector<u64> hS(2 * nbg), hcnt(2 * nbg), hP(nbg);
     u64 Wmax = (u64)W;
     if (batch) {
         for (int64_t g = 0; g < nbg; g++) nver[g] = H->vbase[g + 1] - H->vbase[g];
@@ -719,11 +721,62 @@ louvain_status Runner::run() {
         const int mode = sync ? 0 : (P.async_coherent ? 2 : 1);
         bool sweep = learned;          // LEARNED: iteration 0 is a sweep
         int64_t smp_lo = 0, smp_hi = 0;  // samples recorded for the current iteration
+        // learned pruner (or sample recording): features and MLP over the
+        // vertices flagged by iteration t, then the queue of iteration t + 1
+        // from the kept flags (vertices of stopped graphs are left out)
+        auto filter_next = [&](int t, uint32_t stamp_next, uint8_t* fnext, int32_t* qnext, IterTotals* itp,
+                               int64_t* kept_out) -> louvain_status {
+            Ctl* hc = (Ctl*)H->pinned;
+            const int64_t before = H->smp_count;
+            FilterArgs fa{};
+            fa.off = L.off;
+            fa.n = n;
+            fa.K = K;
+            fa.own = f_own;
+            fa.adv = f_adv;
+            fa.moved = f_moved;
+            fa.nm = f_nm;
+            fa.itag_prev = stamp_next;
+            fa.pass = pass;
+            fa.t = t + 1;
+            fa.flags = fnext;
+            fa.all = prune ? 0 : 1;
+            fa.learned = learned;
+            fa.weights = P.pruner_weights;
+            fa.zt = zt;
+            fa.samples = H->smp_buf;
+            fa.cap = H->smp_buf ? H->smp_cap : 0;
+            fa.per_mille = H->smp_buf ? H->smp_rate : 0;
+            fa.ctl = ctl();
+            timed(H, K_LEARN_FILTER, 0, [&] { launch_learn_filter(fa, L.t.off64, s); });
+            if (prune)
+                timed(H, K_QUEUE, 0, [&] {
+                    bucketize_vertices(n, vb, fnext, 1, gid, gact_dev, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
+                });
+            HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
+            HIPCHK(H, hipMemcpyAsync(&hc->nsamples, &ctl()->nsamples, sizeof(u64), hipMemcpyDeviceToHost, s));
+            HIPCHK(H, hipStreamSynchronize(s));
+            *itp = sum_iter(*hc);
+            H->smp_count = std::min<int64_t>((int64_t)hc->nsamples, H->smp_cap);
+            smp_lo = before;
+            smp_hi = H->smp_count;
+            int64_t kept = 0;
+            for (int b = 0; b < NBT; b++) kept += itp->qcount[b];
+            if (H->prof) {
+                const int64_t flagged = prune ? kept + (int64_t)hc->pruned : nonisolated;
+                const int64_t bytes = filter_alg_bytes(L, n, flagged, (int64_t)hc->pruned, smp_hi - smp_lo);
+                for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
+                    if (r->kind == K_LEARN_FILTER) { r->bytes += bytes; break; }
+            }
+            *kept_out = kept;
+            return LOUVAIN_OK;
+        };
         for (int t = 0; t < P.max_iterations; t++) {
             const int pl = P.pick_less > 0 && ((t + P.pick_less / 2) % P.pick_less) == 0;
             HIPCHK(H, hipMemsetAsync(ctl(), 0, CTL_ITER_BYTES, s));
             if (learn) HIPCHK(H, hipMemsetAsync(f_nm, 0, (size_t)n * 4, s));
             if (batch) HIPCHK(H, hipMemsetAsync(Sg_dev, 0, (size_t)nbg * 16, s));
+            if (Pg_dev) HIPCHK(H, hipMemsetAsync(Pg_dev, 0, (size_t)nbg * 8, s));
             const uint32_t stamp_next = ++H->stamp;  // unique tag of this iteration
             uint8_t* fnext = flags + (size_t)(stamp_next & 1) * (size_t)n0;
             const uint8_t* fcur = flags + (size_t)((stamp_next + 1) & 1) * (size_t)n0;
@@ -761,6 +814,7 @@ louvain_status Runner::run() {
             a.Wg = Wg_dev;
             a.gact = gact_dev;
             a.Sg = Sg_dev;
+            a.Pg = Pg_dev;
             a.learn = learn;
             a.itag = stamp_next;
             a.f_own = f_own;
@@ -902,6 +956,7 @@ louvain_status Runner::run() {
             HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
             if (H->prof) HIPCHK(H, hipMemcpyAsync(&hc->bstat, &ctl()->bstat, sizeof(hc->bstat), hipMemcpyDeviceToHost, s));
             if (batch) HIPCHK(H, hipMemcpyAsync(hS.data(), Sg_dev, (size_t)nbg * 16, hipMemcpyDeviceToHost, s));
+            if (Pg_dev) HIPCHK(H, hipMemcpyAsync(hP.data(), Pg_dev, (size_t)nbg * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(H, hipStreamSynchronize(s));
             IterTotals it = sum_iter(*hc);
             const unsigned __int128 S = it.S;
@@ -940,6 +995,54 @@ louvain_status Runner::run() {
             // other iterations may end the pass (SYNC keeps the exact rule)
             const bool may_end = sync || !pl;
             const bool conv = may_end && converged(S, W, P, pass);
+            if (batch && learned) {
+                // LEARNED, batched: a graph's pass ends only at a sweep whose exit
+                // test passes in that graph (no evaluation with a positive best
+                // gain, or the tolerance test); sweeps are taken by all graphs
+                // together, after a non-sweep iteration where any graph passed
+                // the tolerance test or when the filter kept nothing
+                bool changed = false, any = false, want_sweep = false;
+                for (int64_t g = 0; g < nbg; g++) {
+                    if (!act[g]) continue;
+                    const unsigned __int128 Sg = ((unsigned __int128)hS[2 * g + 1] << 64) + hS[2 * g];
+                    const bool conv_g = may_end && converged(Sg, (int64_t)H->Wg[g], P, pass);
+                    if (sweep && (P.guard_tolerance ? conv_g : hP[g] == 0)) {
+                        li_g[g] = t + 1;
+                        act[g] = 0;
+                        changed = true;
+                    } else {
+                        any = true;
+                        if (!sweep && conv_g) want_sweep = true;
+                    }
+                }
+                if (!any) { li = t + 1; break; }
+                if (changed && (st = upload_act()) != LOUVAIN_OK) return st;
+                bool next_sweep = want_sweep;
+                smp_lo = smp_hi = 0;
+                if (!next_sweep && t + 1 < P.max_iterations) {
+                    int64_t kept = 0;
+                    if ((st = filter_next(t, stamp_next, fnext, qnext, &it, &kept)) != LOUVAIN_OK) return st;
+                    if (kept == 0) {
+                        next_sweep = true;
+                    } else {
+                        H->st.pruned += (int64_t)hc->pruned;
+                        csegs[0] = 0;
+                        for (int b = 0; b < NBT; b++) {
+                            counts[b] = it.qcount[b];
+                            csegs[b + 1] = csegs[b] + counts[b];
+                        }
+                        cur_list = qnext;
+                        qsel ^= 1;
+                    }
+                }
+                if (next_sweep) {
+                    cur_list = blist;
+                    for (int b = 0; b < NBT; b++) counts[b] = bcount[b];
+                    for (int b = 0; b <= NBT; b++) csegs[b] = segs[b];
+                }
+                sweep = next_sweep;
+                continue;
+            }
             if (batch) {
                 // per-graph tolerance tests; converged graphs stop moving for this pass
                 bool changed = false, any = false;
@@ -964,49 +1067,8 @@ louvain_status Runner::run() {
                 bool next_sweep = learned && !sweep && conv;
                 smp_lo = smp_hi = 0;
                 if (!next_sweep && t + 1 < P.max_iterations) {
-                    // filter (and sample) the flagged vertices of iteration t + 1
-                    const int64_t before = H->smp_count;
-                    FilterArgs fa{};
-                    fa.off = L.off;
-                    fa.n = n;
-                    fa.K = K;
-                    fa.own = f_own;
-                    fa.adv = f_adv;
-                    fa.moved = f_moved;
-                    fa.nm = f_nm;
-                    fa.itag_prev = stamp_next;
-                    fa.pass = pass;
-                    fa.t = t + 1;
-                    fa.flags = fnext;
-                    fa.all = prune ? 0 : 1;
-                    fa.learned = learned;
-                    fa.weights = P.pruner_weights;
-                    fa.zt = zt;
-                    fa.samples = H->smp_buf;
-                    fa.cap = H->smp_buf ? H->smp_cap : 0;
-                    fa.per_mille = H->smp_buf ? H->smp_rate : 0;
-                    fa.ctl = ctl();
-                    timed(H, K_LEARN_FILTER, 0, [&] { launch_learn_filter(fa, L.t.off64, s); });
-                    if (prune)
-                        timed(H, K_QUEUE, 0, [&] {
-                            bucketize_vertices(n, vb, fnext, 1, gid, gact_dev, blkcnt, blkoff, qnext, ctl()->qcount,
-                                               scan, s);
-                        });
-                    HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
-                    HIPCHK(H, hipMemcpyAsync(&hc->nsamples, &ctl()->nsamples, sizeof(u64), hipMemcpyDeviceToHost, s));
-                    HIPCHK(H, hipStreamSynchronize(s));
-                    it = sum_iter(*hc);
-                    H->smp_count = std::min<int64_t>((int64_t)hc->nsamples, H->smp_cap);
-                    smp_lo = before;
-                    smp_hi = H->smp_count;
                     int64_t kept = 0;
-                    for (int b = 0; b < NBT; b++) kept += it.qcount[b];
-                    if (H->prof) {
-                        const int64_t flagged = prune ? kept + (int64_t)hc->pruned : nonisolated;
-                        const int64_t bytes = filter_alg_bytes(L, n, flagged, (int64_t)hc->pruned, smp_hi - smp_lo);
-                        for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
-                            if (r->kind == K_LEARN_FILTER) { r->bytes += bytes; break; }
-                    }
+                    if ((st = filter_next(t, stamp_next, fnext, qnext, &it, &kept)) != LOUVAIN_OK) return st;
                     if (learned) {
                         if (kept == 0) next_sweep = true;  // nothing kept: certify with a sweep
                         else H->st.pruned += (int64_t)hc->pruned;
@@ -1477,6 +1539,7 @@ louvain_status louvain_collect_samples(louvain_t* h, float* buffer, int64_t capa
     if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
     if (buffer && (capacity < 0 || sample_per_mille < 0 || sample_per_mille > 1000))
         return fail(h, LOUVAIN_ERR_INVALID, "capacity must be >= 0 and sample_per_mille in [0, 1000]");
+    if (buffer && h->nb > 0) return fail(h, LOUVAIN_ERR_INVALID, "sample recording is not supported on a batched handle");
     h->smp_buf = (buffer && sample_per_mille > 0 && capacity > 0) ? buffer : nullptr;
     h->smp_cap = h->smp_buf ? capacity : 0;
     h->smp_rate = h->smp_buf ? sample_per_mille : 0;

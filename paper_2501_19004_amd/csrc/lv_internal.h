@@ -96,6 +96,7 @@ struct MoveArgs {
     const u64* Wg;
     const uint8_t* gact;
     u64* Sg;
+    u64* Pg;                 // batched learned runs: per-graph evaluations with a positive best gain
     // per-vertex state of the learned pruner's features (learn = 1)
     int32_t learn;
     uint32_t itag;           // tag of this iteration, unique within the run

@@ -589,6 +589,21 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
             acc += sh.gain[k];
         }
         if (cur >= 0 && acc != 0) atomic_add_i128(&a.Sg[2 * cur], &a.Sg[2 * cur + 1], acc);
+        if (a.Pg) {
+            // per-graph positive-gain evaluations, one atomic per run of equal graph id
+            int32_t gcur = -1;
+            u64 pos = 0;
+            for (int k = 0; k < NG; k++) {
+                if (sh.arcs[k] < 0 || !sh.pos[k]) continue;
+                if (sh.gi[k] != gcur) {
+                    if (gcur >= 0 && pos) atomicAdd(&a.Pg[gcur], pos);
+                    gcur = sh.gi[k];
+                    pos = 0;
+                }
+                pos++;
+            }
+            if (gcur >= 0 && pos) atomicAdd(&a.Pg[gcur], pos);
+        }
     }
 }
 
@@ -784,6 +799,7 @@ __device__ __forceinline__ void hub_finish(const MoveArgs& a, int32_t h, int32_t
             if (dcs.target >= 0) apply_async<MODE>(a, Wv, v, c, Ki, dcs);
         }
         if (a.Sg && dcs.target >= 0) atomic_add_i128(&a.Sg[2 * gv], &a.Sg[2 * gv + 1], dcs.gain);
+        if (a.Pg && dcs.positive) atomicAdd(&a.Pg[gv], 1ull);
         if (a.learn) note_evaluation(a, v, dcs);
         a.gdec[h] = dcs.target;
         add_block_totals(a.ctl, a.bucket, 1, (u64)deg, (u64)dcs.nd, dcs.target >= 0 ? 1 : 0,

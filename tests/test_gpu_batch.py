@@ -148,3 +148,59 @@ def test_batch_rejects_cross_graph_arcs():
     with pytest.raises(lv.LouvainError):
         L.modularity()
     L.close()
+
+
+def rand_weights(seed, scale=0.4):
+    rng = np.random.default_rng(seed)
+    return torch.from_numpy((rng.standard_normal(lv.MLP_PARAMS) * scale).astype(np.float32)).to(dev())
+
+
+@pytest.mark.parametrize("theta", [0.45, 0.55])
+@pytest.mark.parametrize("guard", [0, 1], ids=["strict", "tolerance"])
+def test_batch_async_learned_quality(theta, guard):
+    """Batched ASYNC runs with the learned pruner: every graph's membership is
+    valid with exact modularity, and over the batch the mean of Q_gpu minus
+    the plain sequential method's Q is at least -0.002."""
+    graphs = mixed_batch() + sbm_batch(24, 6)
+    parts, q, num, den, passes, iters, comms = run_batch(graphs, lv.ASYNC, pruner=lv.PRUNE_LEARNED,
+                                                         pruner_weights=rand_weights(3), pruner_threshold=theta,
+                                                         guard_tolerance=guard)
+    d = []
+    for k, g in enumerate(graphs):
+        assert (num[k], den[k]) == oracle.modularity_parts(g, parts[k]), k
+        assert sorted(set(parts[k].tolist())) == list(range(comms[k])), k
+        d.append(q[k] - oracle.modularity(g, oracle.louvain(g).membership))
+    print(f"Q_gpu - Q_oracle over the batch: mean {np.mean(d):+.5f} worst {min(d):+.5f}")
+    assert np.mean(d) >= -0.002
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5, 1.0])
+def test_batch_learned_strict_guard_leaves_no_positive_move(theta):
+    """Strict guard in a batch: after one pass, in every graph that stopped
+    before the iteration cap, no vertex has a positive-gain move (exact
+    integer gains with the graph's own total weight)."""
+    graphs = [gg.planted_partition(seed=8), gg.ring_of_cliques(8, 5), gg.rmat(9, 8, seed=2),
+              gg.sbm_degree(800, 8, 12.0, seed=3, wmin=1, wmax=4)]
+    parts, q, num, den, passes, iters, comms = run_batch(graphs, lv.ASYNC, pruner=lv.PRUNE_LEARNED,
+                                                         pruner_weights=rand_weights(3), pruner_threshold=theta,
+                                                         guard_tolerance=0, max_passes=1, max_iterations=60)
+    for k, g in enumerate(graphs):
+        assert iters[k] < 60, k
+        C = parts[k]
+        off, idx, w = g.offsets, g.indices, g.weights.astype(np.int64)
+        K = [int(w[off[v]:off[v + 1]].sum()) for v in range(g.n)]
+        W = sum(K)
+        S = {}
+        for v in range(g.n):
+            S[int(C[v])] = S.get(int(C[v]), 0) + K[v]
+        for v in range(g.n):
+            acc = {}
+            for e in range(off[v], off[v + 1]):
+                j = int(idx[e])
+                if j != v:
+                    acc[int(C[j])] = acc.get(int(C[j]), 0) + int(w[e])
+            c = int(C[v])
+            kic = acc.get(c, 0)
+            for dd, kd in acc.items():
+                if dd != c:
+                    assert W * (kd - kic) - K[v] * (S[dd] - S[c] + K[v]) <= 0, (k, v)
