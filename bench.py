@@ -130,17 +130,19 @@ def learned_leg(lv, torch, nnz, off, idx, w, mode, args, q_plain, dt_plain):
                        "dq_vs_plain": round(q - q_plain, 6), "equal_modularity": abs(q - q_plain) <= 0.002,
                        "passes": st.passes, "iterations": st.iterations, "sweeps": st.sweeps, "pruned": st.pruned,
                        "vertices_evaluated": st.vertices_evaluated, "arcs_scanned": st.arcs_scanned}
-    return {"threshold": args.threshold, "strict_guard": legs["strict"], "tolerance_guard": legs["tolerance"],
+    return wts, {"threshold": args.threshold, "strict_guard": legs["strict"], "tolerance_guard": legs["tolerance"],
             "training": {"graphs": "R-MAT scale 18, edge factor 16, seeds 1018-1020", "samples": int(S.shape[0]),
                          "positive_rate": round(pos, 4), "loss_initial": round(loss0, 5), "loss_final": round(loss, 5),
                          "steps": 1500, "batch": 4096, "lr": 3e-3, "seconds": round(t_train, 1)}}
 
 
-def batch_leg(lv, torch, args):
+def batch_leg(lv, torch, args, wts=None):
     """Batched runs: SBM graphs (equal-size communities, 4 to 64 of them,
     average degree uniform in [8, 32], intra/inter degree ratio 4, weights
     uniform in [1, 4]) with vertex counts log-uniform in [200, nmax], graph k
-    generated with seed 4000 + k, all in one batched handle."""
+    generated with seed 4000 + k, all in one batched handle; ASYNC and SYNC
+    plain, and ASYNC with the learned pruner (strict guard) when its weights
+    were trained."""
     import numpy as np
     import graphgen as gg
     t0 = time.time()
@@ -157,8 +159,13 @@ def batch_leg(lv, torch, args):
     out = {"workload": f"{len(graphs)} SBM graphs, vertices log-uniform in [200, {args.batch_nmax}], "
                        f"4-64 communities, average degree U[8,32], intra/inter 4:1, weights U[1,4]",
            "graphs": len(graphs), "vertices": nv, "arcs": na}
-    for mode, name in ((lv.ASYNC, "async"), (lv.SYNC, "sync")):
-        L = lv.Louvain(off, idx, w, vbase=vbase, mode=mode)
+    legs = [(lv.ASYNC, "async", {}), (lv.SYNC, "sync", {})]
+    if wts is not None:
+        legs.append((lv.ASYNC, "async_learned", dict(pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
+                                                     pruner_threshold=args.threshold, guard_tolerance=0)))
+    qo = None
+    for mode, name, extra in legs:
+        L = lv.Louvain(off, idx, w, vbase=vbase, mode=mode, **extra)
         dt, _, _ = timed_batch(L, args.steps, args.warmup)
         q = np.array(L.modularity_batch()[0])
         passes, iters, comms = L.batch_results()
@@ -166,13 +173,18 @@ def batch_leg(lv, torch, args):
         out[name] = {"value": round(na / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
                      "mean_modularity": round(float(q.mean()), 6), "max_passes": int(max(passes)),
                      "max_iterations": int(max(iters))}
+        if name == "async_learned":
+            out[name]["speedup_vs_async"] = round(out["async"]["ms_per_step"] / out[name]["ms_per_step"], 3)
+            out[name]["dq_mean_vs_async"] = round(float(q.mean()) - out["async"]["mean_modularity"], 6)
         if not args.no_cpu_baseline:
             # quality against the sequential oracle on the first 64 graphs
-            import oracle
-            d = []
-            for k, gk in enumerate(graphs[:64]):
-                gk.weights = gk.weights.astype(np.int64)
-                d.append(q[k] - oracle.modularity(gk, oracle.louvain(gk).membership))
+            if qo is None:
+                import oracle
+                qo = []
+                for gk in graphs[:64]:
+                    gk.weights = gk.weights.astype(np.int64)
+                    qo.append(oracle.modularity(gk, oracle.louvain(gk).membership))
+            d = [q[k] - qo[k] for k in range(len(qo))]
             out[name]["dq_vs_oracle_first64"] = {"mean": round(float(np.mean(d)), 6), "min": round(float(min(d)), 6)}
         print(f"[bench] batch {name}: {dt * 1e3:.2f} ms/run, {na / dt / 1e6:.1f} M arcs/s, mean Q {q.mean():.4f}",
               file=sys.stderr, flush=True)
@@ -295,12 +307,12 @@ def main():
     L.close()
     del L
     torch.cuda.empty_cache()
-    learned = None
+    learned = wts = None
     if not args.no_learned:
-        learned = learned_leg(lv, torch, nnz, off, idx, w, mode, args, q, dt)
+        wts, learned = learned_leg(lv, torch, nnz, off, idx, w, mode, args, q, dt)
     batch = None
     if not args.no_batch:
-        batch = batch_leg(lv, torch, args)
+        batch = batch_leg(lv, torch, args, wts)
 
     cpu = None
     if not args.no_cpu_baseline:
