@@ -215,6 +215,7 @@ def main():
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-pruner leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-SBM leg")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the degree-bucket autotuner leg")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-nmax", type=int, default=20000)
     ap.add_argument("--threshold", type=float, default=0.5, help="learned pruner: keep iff sigmoid >= threshold")
@@ -304,6 +305,20 @@ def main():
                         "local_move_ms_per_run": round(tot_ms / args.steps, 3)}
 
     plain_params = (L.params.async_coherent, L.params.async_min_label)
+    tuned = None
+    if not args.no_autotune:
+        # degree-bucket autotuner: candidate move-bucket thresholds, 2 timed runs each
+        cands = [[8, 32, 128, 512, 4096], [8, 32, 128, 1024, 4096], [8, 16, 64, 256, 4096], [4, 16, 64, 512, 4096],
+                 [8, 32, 64, 256, 2048], [16, 32, 128, 512, 4096]]
+        t0 = time.time()
+        best, cms = L.autotune(cands, reps=2)
+        dtt, qt, stt = timed_runs(L, args.steps, args.warmup)
+        tuned = {"candidates": cands, "candidate_ms": [round(x, 3) for x in cms], "best": best,
+                 "bucket_max_degree": cands[best], "value": round(nnz / dtt / 1e6, 2), "unit": "M edges/s",
+                 "ms_per_step": round(dtt * 1e3, 3), "modularity": round(qt, 6),
+                 "speedup_vs_defaults": round(dt / dtt, 3), "tuning_seconds": round(time.time() - t0 - dtt * (args.steps + args.warmup), 1)}
+        print(f"[bench] autotuned buckets {cands[best]}: {dtt * 1e3:.2f} ms/run, Q={qt:.5f} "
+              f"(candidates {[round(x, 2) for x in cms]} ms)", file=sys.stderr, flush=True)
     L.close()
     del L
     torch.cuda.empty_cache()
@@ -363,6 +378,7 @@ def main():
                    "undirected_Medges_per_s": round(nnz / 2 / dt / 1e6, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "autotuned": tuned,
         "learned_pruner": learned,
         "batch": batch,
     }

@@ -241,6 +241,23 @@ louvain_status louvain_modularity(louvain_t* h, double* q, int64_t num[2], int64
 /* Counters of the last run.  s: host. */
 louvain_status louvain_get_stats(louvain_t* h, louvain_stats* s);
 
+/* Degree-bucket autotuner (for callers that run one graph, or one batch,
+ * many times).  candidates: host int32[ncand * 8], candidate c in entries
+ * [8c, 8c + 8) with the meaning of louvain_params.bucket_max_degree (move
+ * buckets; 0 = default, negative = bucket unused, each clamped to the
+ * bucket's table size).  Runs louvain_run reps times per candidate (the
+ * whole method: the timed quantity is the run), keeps the candidate with the
+ * least mean run time for later runs and writes its index to *best and the
+ * mean milliseconds per candidate to ms (host double[ncand]; either may be
+ * NULL).  SYNC results do not depend on the thresholds; ASYNC results may
+ * differ slightly between candidates (another concurrent schedule).  The
+ * handle's membership and statistics are those of the last timed run: call
+ * louvain_run again for a run with the chosen thresholds.  Errors: a run's
+ * status (thresholds restored); LOUVAIN_ERR_INVALID for ncand < 1, reps < 1
+ * or NULL candidates. */
+louvain_status louvain_autotune(louvain_t* h, const int32_t* candidates, int32_t ncand, int32_t reps, int32_t* best,
+                                double* ms);
+
 /* Enable (1) or disable (0) per-kernel HIP-event timing for later runs.
  * Adds two event records per launch; off by default. */
 louvain_status louvain_set_profiling(louvain_t* h, int32_t enable);

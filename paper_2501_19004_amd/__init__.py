@@ -35,7 +35,7 @@ EXPORTED = ["louvain_params_default", "louvain_workspace_size", "louvain_create"
             "louvain_collect_samples", "louvain_sample_count", "louvain_pruner_init", "louvain_pruner_predict",
             "louvain_pruner_loss_grad", "louvain_pruner_scratch_floats", "louvain_pruner_train",
             "louvain_workspace_size_batch", "louvain_create_batch", "louvain_modularity_batch",
-            "louvain_batch_results"]
+            "louvain_batch_results", "louvain_autotune"]
 
 
 class LouvainGraph(ctypes.Structure):
@@ -126,6 +126,9 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_modularity_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_double), _I64P, _I64P]
     lib.louvain_batch_results.restype = ctypes.c_int
     lib.louvain_batch_results.argtypes = [vp, _I32P, _I32P, _I64P]
+    lib.louvain_autotune.restype = ctypes.c_int
+    lib.louvain_autotune.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, _I32P,
+                                     ctypes.POINTER(ctypes.c_double)]
     lib.louvain_collect_samples.restype = ctypes.c_int
     lib.louvain_collect_samples.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32]
     lib.louvain_sample_count.restype = ctypes.c_int
@@ -300,6 +303,20 @@ def louvain_pruner_train(weights_ptr: int, samples_ptr: int, count: int, steps: 
     return float(loss.value)
 
 
+def louvain_autotune(h, candidates, reps: int = 1):
+    """candidates: list of bucket_max_degree lists (up to 8 entries each).
+    Returns (best index, mean ms per candidate)."""
+    nc = len(candidates)
+    arr = (ctypes.c_int32 * (8 * nc))()
+    for c, cand in enumerate(candidates):
+        for k, x in enumerate(cand):
+            arr[8 * c + k] = int(x)
+    best = ctypes.c_int32(-1)
+    ms = (ctypes.c_double * nc)()
+    _check(load_library().louvain_autotune(h, arr, nc, reps, ctypes.byref(best), ms), h)
+    return int(best.value), [float(x) for x in ms]
+
+
 def louvain_destroy(h) -> None:
     if h:
         load_library().louvain_destroy(h)
@@ -377,6 +394,14 @@ class Louvain:
     def batch_results(self):
         """Per-graph (passes, iterations, communities) lists of a batched handle."""
         return louvain_batch_results(self.h, self.count)
+
+    def autotune(self, candidates, reps: int = 1):
+        """Time the candidate bucket thresholds and keep the fastest (see
+        louvain_autotune); returns (best index, mean ms per candidate)."""
+        best, ms = louvain_autotune(self.h, candidates, reps)
+        for k, x in enumerate(candidates[best]):
+            self.params.bucket_max_degree[k] = int(x)
+        return best, ms
 
     def stats(self) -> LouvainStats:
         return louvain_get_stats(self.h)

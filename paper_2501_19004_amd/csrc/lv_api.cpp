@@ -1535,6 +1535,41 @@ louvain_status louvain_set_trace(louvain_t* h, louvain_iter_fn iter_fn, louvain_
     return LOUVAIN_OK;
 }
 
+louvain_status louvain_autotune(louvain_t* h, const int32_t* candidates, int32_t ncand, int32_t reps, int32_t* best,
+                                double* ms) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    if (!candidates || ncand < 1 || reps < 1) return fail(h, LOUVAIN_ERR_INVALID, "need ncand >= 1 candidates and reps >= 1");
+    // each candidate: the move-bucket degree thresholds of louvain_params.bucket_max_degree
+    constexpr int K = 8;
+    const Buckets keep = h->mb;
+    int32_t keep_deg[K];
+    memcpy(keep_deg, h->p.bucket_max_degree, sizeof(keep_deg));
+    int32_t bi = -1;
+    double bt = 0;
+    for (int32_t c = 0; c < ncand; c++) {
+        const int32_t* cand = candidates + (size_t)c * K;
+        h->mb = make_buckets(cand, NB_MOVE, MOVE_CAP, MOVE_DEFAULT_MAX);
+        double tot = 0;
+        for (int32_t r = 0; r < reps; r++) {
+            const louvain_status st = louvain_run(h);
+            if (st != LOUVAIN_OK) {
+                h->mb = keep;
+                memcpy(h->p.bucket_max_degree, keep_deg, sizeof(keep_deg));
+                return st;
+            }
+            tot += h->st.ms_total;
+        }
+        tot /= reps;
+        if (ms) ms[c] = tot;
+        if (bi < 0 || tot < bt) { bi = c; bt = tot; }
+    }
+    const int32_t* win = candidates + (size_t)bi * K;
+    h->mb = make_buckets(win, NB_MOVE, MOVE_CAP, MOVE_DEFAULT_MAX);
+    memcpy(h->p.bucket_max_degree, win, sizeof(keep_deg));
+    if (best) *best = bi;
+    return LOUVAIN_OK;
+}
+
 louvain_status louvain_collect_samples(louvain_t* h, float* buffer, int64_t capacity, int32_t sample_per_mille) {
     if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
     if (buffer && (capacity < 0 || sample_per_mille < 0 || sample_per_mille > 1000))

@@ -169,3 +169,9 @@ def test_batch_create_rejects_bad_arguments(lib):
     assert create([0, 5, 10], 2) == lv.LOUVAIN_ERR_WORKSPACE    # arguments fine, no workspace
     single = lv.louvain_workspace_size(g, p)
     assert lv.louvain_workspace_size_batch(g, 2, p) > single == lv.louvain_workspace_size_batch(g, 0, p)
+
+
+def test_autotune_rejects_bad_arguments(lib):
+    arr = (ctypes.c_int32 * 8)()
+    best = ctypes.c_int32()
+    assert lib.louvain_autotune(None, arr, 1, 1, ctypes.byref(best), None) == lv.LOUVAIN_ERR_INVALID
