@@ -171,8 +171,31 @@ def _mix64(z: int) -> int:
     return z ^ (z >> 31)
 
 
+class _TupleKernels:
+    """The two tuple kernels of libgraphgen_hip.so on the current stream of
+    `device`, called with torch tensors."""
+
+    def __init__(self, device):
+        import torch
+        self.lib = _load_device()
+        self.stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+    @staticmethod
+    def _p(t):
+        return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+    def hist(self, scale, nt, a, ab, abc, base, perm, shift, hist):
+        if self.lib.gg_dev_rmat_hist(scale, nt, a, ab, abc, base, self._p(perm), shift, self._p(hist), self.stream):
+            raise RuntimeError("device R-MAT histogram failed")
+
+    def select(self, scale, nt, a, ab, abc, base, perm, shift, blo, bhi, out, cnt):
+        if self.lib.gg_dev_rmat_select(scale, nt, a, ab, abc, base, self._p(perm), shift, blo, bhi, self._p(out),
+                                       out.numel(), self._p(cnt), self.stream):
+            raise RuntimeError("device R-MAT selection failed")
+
+
 def rmat_device(scale: int, edge_factor: int, a=0.57, b=0.19, c=0.19, seed: int = 22, permute: bool = True,
-                device="cuda", round_cap: int = 1 << 28):
+                device="cuda", round_cap: int = 1 << 28, kernels=None):
     """R-MAT graph built on the GPU: the same graph as ``rmat`` (unit weights).
 
     Returns (offsets int64 [n+1], indices int32 [nnz]) as device tensors.  The
@@ -182,29 +205,27 @@ def rmat_device(scale: int, edge_factor: int, a=0.57, b=0.19, c=0.19, seed: int 
     then laid out as a symmetric CSR with ascending rows, again in rounds of
     at most ``round_cap`` arcs.  Peak device memory is about
     8 B x unique edges + 4 B x arcs + a few x 8 B x round_cap.
+    ``kernels`` replaces the two tuple kernels (hist, select), for tests.
     """
     import torch
 
-    lib = _load_device()
     n = 1 << scale
     nt = edge_factor * n
     dev = torch.device(device)
-    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    kern = kernels if kernels is not None else _TupleKernels(dev)
     perm_d = None
     if permute:
         perm = np.empty(n, dtype=np.int32)
         _load().gg_perm(n, seed, _ptr(perm, ctypes.c_int32))
         perm_d = torch.from_numpy(perm).to(dev)
         del perm
-    pptr = ctypes.c_void_p(perm_d.data_ptr() if perm_d is not None else 0)
     base = _mix64(seed ^ _mix64(_ST_RMAT))
     ab = a + b
     abc = a + b + c
     shift = max(0, scale - 12)
     nbins = 1 << (scale - shift)
     hist = torch.zeros(nbins, dtype=torch.int64, device=dev)
-    if lib.gg_dev_rmat_hist(scale, nt, a, ab, abc, base, pptr, shift, ctypes.c_void_p(hist.data_ptr()), stream):
-        raise RuntimeError("device R-MAT histogram failed")
+    kern.hist(scale, nt, a, ab, abc, base, perm_d, shift, hist)
     h = hist.cpu().numpy()
     if h.max(initial=0) > round_cap:
         raise RuntimeError("one R-MAT key bin exceeds round_cap; raise round_cap")
@@ -223,10 +244,7 @@ def rmat_device(scale: int, edge_factor: int, a=0.57, b=0.19, c=0.19, seed: int 
         if expect == 0:
             continue
         cnt.zero_()
-        if lib.gg_dev_rmat_select(scale, nt, a, ab, abc, base, pptr, shift, blo, bhi,
-                                  ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.c_void_p(cnt.data_ptr()),
-                                  stream):
-            raise RuntimeError("device R-MAT selection failed")
+        kern.select(scale, nt, a, ab, abc, base, perm_d, shift, blo, bhi, buf, cnt)
         k = int(cnt.item())
         if k != expect:
             raise RuntimeError(f"device R-MAT round found {k} keys, histogram said {expect}")

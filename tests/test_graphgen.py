@@ -73,3 +73,60 @@ def test_sbm_degree_parameters():
     same = g.labels[np.repeat(np.arange(g.n), np.diff(g.offsets))] == g.labels[g.indices]
     assert abs(same.mean() - 0.8) < 0.02      # intra:inter = 4:1
     assert g.weights.min() >= 1 and g.weights.max() <= 4
+
+
+class _NumpyTupleKernels:
+    """The device generator's two tuple kernels redone in numpy on the host:
+    the R-MAT draw of every tuple from the published SplitMix64 stream."""
+
+    @staticmethod
+    def _keys(scale, nt, a, ab, abc, base, perm):
+        def mix(z):
+            z = z + np.uint64(0x9E3779B97F4A7C15)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            return z ^ (z >> np.uint64(31))
+        k = np.arange(nt, dtype=np.uint64)
+        u = np.zeros(nt, np.int64)
+        v = np.zeros(nt, np.int64)
+        with np.errstate(over="ignore"):
+            for lvl in range(scale):
+                r = (mix(np.uint64(base) + k * np.uint64(scale) + np.uint64(lvl)) >> np.uint64(11)).astype(np.float64)
+                r *= 1.0 / 9007199254740992.0
+                u = (u << 1) | (r >= ab)
+                v = (v << 1) | (((r >= a) & (r < ab)) | (r >= abc))
+        if perm is not None:
+            p = perm.cpu().numpy().astype(np.int64)
+            u, v = p[u], p[v]
+        keep = u != v
+        lo, hi = np.minimum(u, v)[keep], np.maximum(u, v)[keep]
+        return lo, (lo << scale) | hi
+
+    def hist(self, scale, nt, a, ab, abc, base, perm, shift, hist):
+        import torch
+        lo, _ = self._keys(scale, nt, a, ab, abc, base, perm)
+        hist.copy_(torch.from_numpy(np.bincount(lo >> shift, minlength=hist.numel())))
+
+    def select(self, scale, nt, a, ab, abc, base, perm, shift, blo, bhi, out, cnt):
+        import torch
+        lo, keys = self._keys(scale, nt, a, ab, abc, base, perm)
+        b = lo >> shift
+        sel = keys[(b >= blo) & (b < bhi)]
+        np.random.default_rng(0).shuffle(sel)  # the device appends in no fixed order
+        k = min(out.numel(), sel.size)
+        out[:k] = torch.from_numpy(sel[:k])
+        cnt[0] = sel.size
+
+
+@pytest.mark.parametrize("scale,ef,seed,permute,cap", [(10, 8, 3, True, 1 << 20), (12, 16, 22, True, 1 << 11),
+                                                       (11, 4, 9, False, 1 << 10)])
+def test_device_rmat_rounds_and_layout_on_host(scale, ef, seed, permute, cap):
+    """The device generator's host-side logic (key rounds, deduplication,
+    symmetric CSR rounds) with its two kernels replaced by a numpy draw of
+    the same tuples equals the host generator; small rounds force several."""
+    torch = pytest.importorskip("torch")
+    off, idx = gg.rmat_device(scale, ef, seed=seed, permute=permute, device="cpu", round_cap=cap,
+                              kernels=_NumpyTupleKernels())
+    g = gg.rmat(scale, ef, seed=seed, permute=permute)
+    assert np.array_equal(off.numpy(), g.offsets)
+    assert np.array_equal(idx.numpy(), g.indices)
