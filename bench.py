@@ -10,9 +10,11 @@ One step = one complete louvain_run on the device-resident graph.  The
 metric counts stored arcs (each undirected edge twice), as the paper does.
 The timed steps run without per-kernel events; the same number of steps is
 then repeated with HIP events around every launch for the roofline figures.
-A second leg trains the learned move-pruner on samples recorded from
-separate R-MAT graphs (seeds 1018-1020) and times the same workload with it.
-Prints one JSON line.
+Further legs: the degree-bucket autotuner (candidate thresholds timed by
+louvain_autotune, then the workload timed with the winner); the learned
+move-pruner, trained on samples recorded from separate R-MAT graphs (seeds
+1018-1020), with both sweep guards; 4096 batched SBM graphs (ASYNC, SYNC,
+ASYNC with the learned pruner).  Prints one JSON line.
 
 Other workloads (--workload): grid4096, planted, rmatS (S <= 24, edge factor
 16), and rmat27: R-MAT scale 27, edge factor 28, seed 27 (134M vertices,
