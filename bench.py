@@ -230,7 +230,7 @@ def main():
                     help="ASYNC: device-coherent loads of C' and Sigma' (1) or cached loads (0, library default)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the Louvain library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np

@@ -1,7 +1,7 @@
 /*
  * louvain_oracle.c -- plain, sequential CPU oracle for the Louvain method.
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the correctness judge for the GPU
+ * TEST INFRASTRUCTURE ONLY.  This file is the correctness reference for the GPU
  * path: only the test suite, the smoke check and the benchmark's CPU-baseline
  * leg may load it.  It shares no code, header or constant with the GPU
  * library.
