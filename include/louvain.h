@@ -149,7 +149,7 @@ typedef struct {
     /* ASYNC only: the hubs (vertices above the largest LDS bucket) of an
      * iteration are processed in this many id-ordered groups, group k right
      * after slice floor((k + 1) * slices / groups) - 1; 0 = one group per
-     * slice; default 16. */
+     * slice; default 32. */
     int32_t async_hub_groups;
     /* ASYNC only: 1 = a vertex alone in its community does not join another
      * single-vertex community of larger id (the pair merges the other way),

@@ -345,7 +345,7 @@ void louvain_params_default(louvain_params* p) {
     p->async_slice_iters = 0;
     p->guard_tolerance = 0;
     p->async_slice_min = 32;
-    p->async_hub_groups = 16;
+    p->async_hub_groups = 32;
     p->async_min_label = 1;
     p->async_interleave = 0;
     p->pruner_weights = nullptr;
