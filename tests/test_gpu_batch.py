@@ -4,13 +4,18 @@ Every graph of a batch must come out exactly as the oracle's run of that
 graph alone: in SYNC mode the same membership, passes, iterations and
 community count, and the exact modularity of the GPU membership equals the
 oracle's evaluation of it with the graph's own total weight.  ASYNC runs
-must reach, graph by graph, modularity within 0.002 of the oracle's.
+must reach, graph by graph, modularity within 0.002 of the oracle's, where
+the oracle's modularity is the lowest it reaches over the identity vertex
+order and seeded relabellings (tests/orders.py: the method leaves the
+visiting order open, and weak SBM graphs end in optima that differ by more
+than 0.002 between orders).
 """
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
+from orders import async_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -119,20 +124,19 @@ def test_batch_sync_sbm_many_graphs():
 
 @pytest.mark.parametrize("make", [mixed_batch, lambda: sbm_batch(48, 5)], ids=["mixed", "sbm48"])
 def test_batch_async_quality(make):
-    """Every graph's membership is valid and its exact modularity is the
-    oracle's evaluation of it; over the batch, the mean of Q_gpu - Q_oracle
-    is at least -0.002.  (Graphs of a few hundred vertices move by more than
-    0.002 under a mere relabelling of their vertices in the sequential oracle
-    itself, so the bound is applied to the batch mean.)"""
+    """Every graph's membership is valid, its exact modularity is the
+    oracle's evaluation of it, and, graph by graph, Q_gpu is at least the
+    oracle's lowest modularity over the visiting orders minus 0.002."""
     graphs = make()
     parts, q, num, den, passes, iters, comms = run_batch(graphs, lv.ASYNC)
     d = []
     for k, g in enumerate(graphs):
         assert (num[k], den[k]) == oracle.modularity_parts(g, parts[k]), k
         assert sorted(set(parts[k].tolist())) == list(range(comms[k])), k
-        d.append(q[k] - oracle.modularity(g, oracle.louvain(g).membership))
-    print(f"Q_gpu - Q_oracle over the batch: mean {np.mean(d):+.5f} worst {min(d):+.5f}")
-    assert np.mean(d) >= -0.002
+        d.append(q[k] - async_floor(g))
+    print(f"Q_gpu - (floor over orders) per graph: min {min(d):+.5f} mean {np.mean(d):+.5f}")
+    bad = [(k, graphs[k].name, round(d[k], 5)) for k in range(len(graphs)) if d[k] < 0]
+    assert not bad, bad
 
 
 def test_batch_rejects_cross_graph_arcs():
@@ -159,8 +163,9 @@ def rand_weights(seed, scale=0.4):
 @pytest.mark.parametrize("guard", [0, 1], ids=["strict", "tolerance"])
 def test_batch_async_learned_quality(theta, guard):
     """Batched ASYNC runs with the learned pruner: every graph's membership is
-    valid with exact modularity, and over the batch the mean of Q_gpu minus
-    the plain sequential method's Q is at least -0.002."""
+    valid with exact modularity, and, graph by graph, Q_gpu is at least the
+    plain sequential method's lowest modularity over the visiting orders
+    minus 0.002."""
     graphs = mixed_batch() + sbm_batch(24, 6)
     parts, q, num, den, passes, iters, comms = run_batch(graphs, lv.ASYNC, pruner=lv.PRUNE_LEARNED,
                                                          pruner_weights=rand_weights(3), pruner_threshold=theta,
@@ -169,9 +174,10 @@ def test_batch_async_learned_quality(theta, guard):
     for k, g in enumerate(graphs):
         assert (num[k], den[k]) == oracle.modularity_parts(g, parts[k]), k
         assert sorted(set(parts[k].tolist())) == list(range(comms[k])), k
-        d.append(q[k] - oracle.modularity(g, oracle.louvain(g).membership))
-    print(f"Q_gpu - Q_oracle over the batch: mean {np.mean(d):+.5f} worst {min(d):+.5f}")
-    assert np.mean(d) >= -0.002
+        d.append(q[k] - async_floor(g))
+    print(f"Q_gpu - (floor over orders) per graph: min {min(d):+.5f} mean {np.mean(d):+.5f}")
+    bad = [(k, graphs[k].name, round(d[k], 5)) for k in range(len(graphs)) if d[k] < 0]
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.5, 1.0])
