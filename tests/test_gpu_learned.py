@@ -244,6 +244,33 @@ def test_mlp_train_one_full_batch_step_is_adam():
     assert np.allclose(w.cpu().numpy()[moved], w64[moved], atol=2e-4)
 
 
+@pytest.mark.parametrize("steps", [3, 5])
+def test_mlp_train_full_batch_steps_follow_float64_adam(steps):
+    """Several full-batch Adam steps (moments carried from step to step,
+    bias corrections 1 - beta^k) against the float64 iteration of the same
+    loss, compared on the parameters whose float64 gradient is clearly away
+    from zero at every step (there both Adam directions are well conditioned)."""
+    S = _samples(600, 7)
+    wts = rand_weights(8)
+    w = torch.from_numpy(wts.copy()).to(dev())
+    lr = 0.01
+    lv.pruner_train(w, torch.from_numpy(S).to(dev()), steps=steps, batch=4096, lr=lr, pos_weight=1.5)
+    w64 = wts.astype(np.float64)
+    m = np.zeros_like(w64)
+    v = np.zeros_like(w64)
+    gmin = np.full_like(w64, np.inf)
+    for k in range(1, steps + 1):
+        _, g64 = mlp.loss_grad(w64, S[:, :8], S[:, 8], 1.5)
+        gmin = np.minimum(gmin, np.abs(g64))
+        w64, m, v = mlp.adam_step(w64, g64, m, v, k, lr)
+    clear = gmin > 1e-3
+    assert clear.sum() > 200
+    got = w.cpu().numpy().astype(np.float64)
+    assert np.allclose(got[clear], w64[clear], atol=5e-4 * steps)
+    # the parameters moved by about steps * lr, not by one step's worth
+    assert np.median(np.abs(got[clear] - wts[clear])) > 0.5 * steps * lr
+
+
 def test_mlp_training_reduces_loss():
     S = _samples(20000, 2)
     w = lv.pruner_init(3, dev())

@@ -117,6 +117,37 @@ def test_adam_first_step_is_signed_lr():
     assert w[3] == 0.0
 
 
+@pytest.mark.parametrize("steps", [2, 3, 10, 100])
+def test_adam_constant_gradient_closed_form(steps):
+    """With the same gradient g at every step, both bias-corrected moments
+    equal g and g^2 exactly (m_k = (1 - beta1^k) g, v_k = (1 - beta2^k) g^2),
+    so every step moves w by lr * g / (|g| + eps): w_k = w_0 - k lr g / (|g| + eps).
+    A wrong bias-correction exponent or moment recurrence breaks this from
+    step 2 on."""
+    g = np.array([0.3, -2.0, 1e-3, 5e-7, 0.0])
+    lr = 0.01
+    w, m, v = np.full(5, 0.25), np.zeros(5), np.zeros(5)
+    for k in range(1, steps + 1):
+        w, m, v = mlp.adam_step(w, g, m, v, k, lr)
+    expect = 0.25 - steps * lr * g / (np.abs(g) + mlp.EPS)
+    assert np.allclose(w, expect, rtol=1e-12, atol=1e-14)
+
+
+def test_adam_two_steps_varying_gradient_closed_form():
+    """Two steps with gradients a then b: m_hat = (beta1 a + b) / (1 + beta1)
+    and v_hat = (beta2 a^2 + b^2) / (1 + beta2) (the moment recurrences
+    unrolled by hand), after a first step of -lr * sign(a)."""
+    a = np.array([0.5, -1.0, 2.0, 1e-2])
+    b = np.array([-0.25, -3.0, 0.5, 1e-2])
+    lr, b1, b2 = 0.03, 0.9, 0.999
+    w, m, v = mlp.adam_step(np.zeros(4), a, np.zeros(4), np.zeros(4), 1, lr)
+    w, m, v = mlp.adam_step(w, b, m, v, 2, lr)
+    w1 = -lr * a / (np.abs(a) + mlp.EPS)
+    mh = (b1 * a + b) / (1 + b1)
+    vh = (b2 * a * a + b * b) / (1 + b2)
+    assert np.allclose(w, w1 - lr * mh / (np.sqrt(vh) + mlp.EPS), rtol=1e-12, atol=1e-15)
+
+
 def test_glorot_init_bounds():
     w = mlp.glorot_init(11)
     W1, b1, W2, b2, w3, b3 = mlp.unpack(w)
