@@ -245,16 +245,22 @@ louvain_status louvain_get_stats(louvain_t* h, louvain_stats* s);
  * many times).  candidates: host int32[ncand * 8], candidate c in entries
  * [8c, 8c + 8) with the meaning of louvain_params.bucket_max_degree (move
  * buckets; 0 = default, negative = bucket unused, each clamped to the
- * bucket's table size).  Runs louvain_run reps times per candidate (the
- * whole method: the timed quantity is the run), keeps the candidate with the
- * least mean run time for later runs and writes its index to *best and the
- * mean milliseconds per candidate to ms (host double[ncand]; either may be
- * NULL).  SYNC results do not depend on the thresholds; ASYNC results may
- * differ slightly between candidates (another concurrent schedule).  The
- * handle's membership and statistics are those of the last timed run: call
- * louvain_run again for a run with the chosen thresholds.  Errors: a run's
- * status (thresholds restored); LOUVAIN_ERR_INVALID for ncand < 1, reps < 1
- * or NULL candidates. */
+ * bucket's table size).  The handle's current thresholds are the baseline:
+ * they and every candidate are timed over reps runs of louvain_run (the
+ * whole method: the timed quantity is the run).  A candidate is eligible if
+ * its lowest modularity over its runs (Eq. (1); the mean over the graphs of
+ * a batched handle) is at most 0.002 below the baseline's lowest.  The
+ * fastest eligible candidate whose mean run time beats the baseline's mean
+ * by more than the baseline's own spread (slowest minus fastest of its reps;
+ * use reps >= 3 for a meaningful spread) is kept for later runs and its index
+ * written to *best; otherwise the thresholds stay as they were and *best =
+ * -1.  ms (host double[ncand]) receives each candidate's mean milliseconds.
+ * best and ms may be NULL.  SYNC results do not depend on the thresholds;
+ * ASYNC results may differ slightly between candidates (another concurrent
+ * schedule).  The handle's membership and statistics are those of the last
+ * timed run: call louvain_run again for a run with the chosen thresholds.
+ * Errors: a run's status (thresholds restored); LOUVAIN_ERR_INVALID for
+ * ncand < 1, reps < 1 or NULL candidates. */
 louvain_status louvain_autotune(louvain_t* h, const int32_t* candidates, int32_t ncand, int32_t reps, int32_t* best,
                                 double* ms);
 

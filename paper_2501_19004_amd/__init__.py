@@ -305,7 +305,8 @@ def louvain_pruner_train(weights_ptr: int, samples_ptr: int, count: int, steps: 
 
 def louvain_autotune(h, candidates, reps: int = 1):
     """candidates: list of bucket_max_degree lists (up to 8 entries each).
-    Returns (best index, mean ms per candidate)."""
+    Returns (index of the kept candidate or -1 when the handle's thresholds
+    stay, mean ms per candidate)."""
     nc = len(candidates)
     arr = (ctypes.c_int32 * (8 * nc))()
     for c, cand in enumerate(candidates):
@@ -324,6 +325,29 @@ def louvain_destroy(h) -> None:
 
 # --------------------------------------------------------- torch plumbing
 
+def _check_graph_tensors(offsets, indices, weights):
+    """The C ABI reads raw device pointers: reject tensors whose dtype,
+    layout or device would make it read a different graph than the caller's."""
+    import torch
+    dev = offsets.device
+    for name, t, dtypes in (("offsets", offsets, (torch.int32, torch.int64)), ("indices", indices, (torch.int32,)),
+                            ("weights", weights, (torch.int32,))):
+        if t is None:
+            if name == "weights":
+                continue
+            raise ValueError(f"{name} is required")
+        if t.dtype not in dtypes:
+            raise ValueError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+        if not t.is_cuda or t.device != dev:
+            raise ValueError(f"{name} must be a CUDA tensor on {dev}, got {t.device}")
+        if not t.is_contiguous() or t.dim() != 1:
+            raise ValueError(f"{name} must be a contiguous 1-D tensor")
+    if offsets.numel() < 1:
+        raise ValueError("offsets must hold n + 1 >= 1 entries")
+    if weights is not None and weights.numel() != indices.numel():
+        raise ValueError("weights and indices must have the same length")
+
+
 class Louvain:
     """A handle on one device-resident graph.
 
@@ -338,6 +362,7 @@ class Louvain:
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU available: the Louvain library runs only on the GPU")
         load_library()
+        _check_graph_tensors(offsets, indices, weights)
         self._keep = (offsets, indices, weights, overrides.get("pruner_weights"))
         self.params = params or louvain_params_default()
         for k, v in overrides.items():
@@ -399,8 +424,9 @@ class Louvain:
         """Time the candidate bucket thresholds and keep the fastest (see
         louvain_autotune); returns (best index, mean ms per candidate)."""
         best, ms = louvain_autotune(self.h, candidates, reps)
-        for k, x in enumerate(candidates[best]):
-            self.params.bucket_max_degree[k] = int(x)
+        if best >= 0:
+            for k, x in enumerate(candidates[best]):
+                self.params.bucket_max_degree[k] = int(x)
         return best, ms
 
     def stats(self) -> LouvainStats:

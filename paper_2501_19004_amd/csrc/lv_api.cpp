@@ -12,11 +12,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -179,6 +181,8 @@ struct louvain_s {
     std::string err = "no error";
     void* pinned = nullptr;  // readback staging
     void* pinned_up = nullptr;  // upload staging
+    bool stage_owned = true;    // pinned/pinned_up were allocated by create (else fixed host buffers)
+    bool handle_owned = true;   // the handle itself was allocated by create (else placed in fixed storage)
     louvain_iter_fn itfn = nullptr;
     louvain_pass_fn pafn = nullptr;
     void* user = nullptr;
@@ -372,8 +376,11 @@ louvain_status louvain_workspace_size_batch(const louvain_graph* g, int64_t coun
 
 namespace {
 
+// stage/stage_up: fixed host staging buffers (1 MiB and 64 KiB) to use instead
+// of allocating pinned ones, or nullptr.
 louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t count, const louvain_params* p,
-                           void* stream, void* workspace, size_t workspace_bytes, louvain_t** out) {
+                           void* stream, void* workspace, size_t workspace_bytes, louvain_t** out,
+                           void* stage = nullptr, void* stage_up = nullptr, void* handle_mem = nullptr) {
     if (!out) return fail(nullptr, LOUVAIN_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!g || !p) return fail(nullptr, LOUVAIN_ERR_INVALID, "null graph or params");
@@ -411,8 +418,9 @@ louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t
         return fail(nullptr, LOUVAIN_ERR_WORKSPACE, "workspace must be %zu bytes, 256-byte aligned (got %zu)",
                     lay.total, workspace_bytes);
 
-    louvain_t* h = new (std::nothrow) louvain_s();
+    louvain_t* h = handle_mem ? new (handle_mem) louvain_s() : new (std::nothrow) louvain_s();
     if (!h) return fail(nullptr, LOUVAIN_ERR_NOMEM, "handle allocation failed");
+    h->handle_owned = handle_mem == nullptr;
     h->stream = (hipStream_t)stream;
     h->g = *g;
     h->p = *p;
@@ -436,8 +444,12 @@ louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t
         louvain_destroy(h);
         return st;
     };
-    if (hipHostMalloc(&h->pinned, 1 << 20, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&h->pinned_up, 1 << 16, hipHostMallocDefault) != hipSuccess) {
+    if (stage && stage_up) {
+        h->pinned = stage;
+        h->pinned_up = stage_up;
+        h->stage_owned = false;
+    } else if (hipHostMalloc(&h->pinned, 1 << 20, hipHostMallocDefault) != hipSuccess ||
+               hipHostMalloc(&h->pinned_up, 1 << 16, hipHostMallocDefault) != hipSuccess) {
         h->err = "pinned host allocation failed";
         return bail(LOUVAIN_ERR_HIP);
     }
@@ -643,6 +655,7 @@ louvain_status Runner::run() {
         if (nbg <= (1 << 16)) {
             memcpy(H->pinned_up, act.data(), (size_t)nbg);
             HIPCHK(H, hipMemcpyAsync(gact_dev, H->pinned_up, (size_t)nbg, hipMemcpyHostToDevice, s));
+            if (!H->stage_owned) HIPCHK(H, hipStreamSynchronize(s));  // pageable source: reused next time
         } else {
             HIPCHK(H, hipMemcpyAsync(gact_dev, act.data(), (size_t)nbg, hipMemcpyHostToDevice, s));
             HIPCHK(H, hipStreamSynchronize(s));
@@ -1370,24 +1383,8 @@ louvain_status Runner::run() {
     return LOUVAIN_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-louvain_status louvain_run(louvain_t* h) {
-    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
-    hipEvent_t e0, e1;
-    HIPCHK(h, hipEventCreate(&e0));
-    HIPCHK(h, hipEventCreate(&e1));
-    HIPCHK(h, hipEventRecord(e0, h->stream));
-    Runner r(h);
-    louvain_status st = r.run();
-    (void)hipEventRecord(e1, h->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+// After a run: wall time, per-kernel records (profiling), run counters.
+louvain_status finish_run(louvain_t* h, louvain_status st, double ms) {
     if (st != LOUVAIN_OK) { h->ran = false; return st; }
     h->st.ms_total = ms;
     // per-kernel timing
@@ -1415,6 +1412,27 @@ louvain_status louvain_run(louvain_t* h) {
     }
     h->ran = true;
     return LOUVAIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+louvain_status louvain_run(louvain_t* h) {
+    if (!h) return fail(nullptr, LOUVAIN_ERR_INVALID, "null handle");
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    HIPCHK(h, hipEventRecord(e0, h->stream));
+    Runner r(h);
+    louvain_status st = r.run();
+    (void)hipEventRecord(e1, h->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return finish_run(h, st, ms);
 }
 
 louvain_status louvain_get_membership(louvain_t* h, int32_t* out) {
@@ -1544,28 +1562,68 @@ louvain_status louvain_autotune(louvain_t* h, const int32_t* candidates, int32_t
     const Buckets keep = h->mb;
     int32_t keep_deg[K];
     memcpy(keep_deg, h->p.bucket_max_degree, sizeof(keep_deg));
+    // modularity of the handle's last run (the batch mean for a batched handle)
+    std::vector<double> qb(h->nb > 0 ? (size_t)h->nb : 1);
+    auto last_q = [&](double* q) -> louvain_status {
+        if (h->nb > 0) {
+            const louvain_status st = louvain_modularity_batch(h, qb.data(), nullptr, nullptr);
+            if (st != LOUVAIN_OK) return st;
+            double m = 0;
+            for (double x : qb) m += x;
+            *q = m / (double)qb.size();
+            return LOUVAIN_OK;
+        }
+        return louvain_modularity(h, q, nullptr, nullptr);
+    };
+    // reps timed runs with the current buckets: mean and spread of the times, lowest Q
+    auto measure = [&](double* mean, double* spread, double* qmin) -> louvain_status {
+        double tot = 0, lo = 0, hi = 0;
+        *qmin = 0;
+        for (int32_t r = 0; r < reps; r++) {
+            louvain_status st = louvain_run(h);
+            double q = 0;
+            if (st == LOUVAIN_OK) st = last_q(&q);
+            if (st != LOUVAIN_OK) return st;
+            const double t = h->st.ms_total;
+            tot += t;
+            lo = r == 0 ? t : std::min(lo, t);
+            hi = r == 0 ? t : std::max(hi, t);
+            *qmin = r == 0 ? q : std::min(*qmin, q);
+        }
+        *mean = tot / reps;
+        *spread = hi - lo;
+        return LOUVAIN_OK;
+    };
+    auto restore = [&](louvain_status st) {
+        h->mb = keep;
+        memcpy(h->p.bucket_max_degree, keep_deg, sizeof(keep_deg));
+        return st;
+    };
+    // the handle's own thresholds are the baseline every candidate must beat
+    double base_t = 0, base_spread = 0, base_q = 0;
+    louvain_status st0 = measure(&base_t, &base_spread, &base_q);
+    if (st0 != LOUVAIN_OK) return restore(st0);
     int32_t bi = -1;
-    double bt = 0;
+    double bt = base_t - base_spread;
     for (int32_t c = 0; c < ncand; c++) {
         const int32_t* cand = candidates + (size_t)c * K;
         h->mb = make_buckets(cand, NB_MOVE, MOVE_CAP, MOVE_DEFAULT_MAX);
-        double tot = 0;
-        for (int32_t r = 0; r < reps; r++) {
-            const louvain_status st = louvain_run(h);
-            if (st != LOUVAIN_OK) {
-                h->mb = keep;
-                memcpy(h->p.bucket_max_degree, keep_deg, sizeof(keep_deg));
-                return st;
-            }
-            tot += h->st.ms_total;
-        }
-        tot /= reps;
-        if (ms) ms[c] = tot;
-        if (bi < 0 || tot < bt) { bi = c; bt = tot; }
+        double t = 0, spread = 0, q = 0;
+        const louvain_status st = measure(&t, &spread, &q);
+        if (st != LOUVAIN_OK) return restore(st);
+        if (ms) ms[c] = t;
+        // a candidate may not buy its speed with modularity (ASYNC runs can
+        // converge early to a worse optimum): at most 0.002 below the baseline
+        if (q < base_q - 0.002) continue;
+        if (t < bt) { bi = c; bt = t; }
     }
-    const int32_t* win = candidates + (size_t)bi * K;
-    h->mb = make_buckets(win, NB_MOVE, MOVE_CAP, MOVE_DEFAULT_MAX);
-    memcpy(h->p.bucket_max_degree, win, sizeof(keep_deg));
+    if (bi < 0) {
+        restore(LOUVAIN_OK);
+    } else {
+        const int32_t* win = candidates + (size_t)bi * K;
+        h->mb = make_buckets(win, NB_MOVE, MOVE_CAP, MOVE_DEFAULT_MAX);
+        memcpy(h->p.bucket_max_degree, win, sizeof(keep_deg));
+    }
     if (best) *best = bi;
     return LOUVAIN_OK;
 }
@@ -1689,9 +1747,10 @@ void louvain_destroy(louvain_t* h) {
     if (h->stream) hipStreamSynchronize(h->stream);
     else hipDeviceSynchronize();
     for (auto e : h->evpool) hipEventDestroy(e);
-    if (h->pinned) hipHostFree(h->pinned);
-    if (h->pinned_up) hipHostFree(h->pinned_up);
-    delete h;
+    if (h->stage_owned && h->pinned) hipHostFree(h->pinned);
+    if (h->stage_owned && h->pinned_up) hipHostFree(h->pinned_up);
+    if (h->handle_owned) delete h;
+    else h->~louvain_s();
 }
 
 }  // extern "C"

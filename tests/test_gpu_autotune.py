@@ -1,5 +1,6 @@
-"""Degree-bucket autotuner: it picks one of the candidate threshold sets by
-measured run time and later runs use it.  SYNC results do not depend on the
+"""Degree-bucket autotuner: it keeps one of the candidate threshold sets when
+it beats the handle's own thresholds by more than their run-to-run spread
+without losing modularity, and later runs use it.  SYNC results do not depend on the
 thresholds, so a tuned SYNC handle must still equal the oracle; a tuned
 ASYNC handle must still meet the modularity bound."""
 import numpy as np
@@ -26,9 +27,10 @@ def test_autotune_sync_keeps_oracle_result():
     g = gg.rmat(12, 16, seed=4, wmax=7)
     off, idx, w = lv.graph_tensors(g, dev())
     L = lv.Louvain(off, idx, w, mode=lv.SYNC)
-    best, ms = L.autotune(CANDIDATES, reps=2)
-    assert 0 <= best < len(CANDIDATES) and all(x > 0 for x in ms)
-    assert ms[best] == min(ms)
+    best, ms = L.autotune(CANDIDATES, reps=3)
+    assert -1 <= best < len(CANDIDATES) and all(x > 0 for x in ms)
+    # SYNC: every candidate has the same modularity, so the kept one is the fastest
+    assert best == -1 or ms[best] == min(ms)
     L.run()
     memb = L.membership().cpu().numpy()
     q, num, den = L.modularity()
@@ -43,7 +45,7 @@ def test_autotune_async_quality():
     g = gg.rmat(14, 16, seed=5)
     off, idx, w = lv.graph_tensors(g, dev())
     L = lv.Louvain(off, idx, w, mode=lv.ASYNC)
-    best, ms = L.autotune(CANDIDATES, reps=1)
+    best, ms = L.autotune(CANDIDATES, reps=3)
     L.run()
     memb = L.membership().cpu().numpy()
     q, num, den = L.modularity()
