@@ -1,39 +1,56 @@
 #!/usr/bin/env python3
-"""Benchmark: plain Louvain (local moving + aggregation, all passes) on one MI355X.
+"""Benchmark: Louvain (local moving + aggregation, all passes) on one MI355X,
+plain against learned-pruned, next to the sequential oracle and a multicore
+CPU baseline on the host.
 
-Workload (default): R-MAT scale 22, edge factor 16 (a/b/c/d = .57/.19/.19/.05,
-seed 22, duplicates and self-loops removed, unit weights, int32 CSR), paper
-defaults (20 iterations, 10 passes, tau 0.01 dropped 10x, tau_agg 0.8,
-Pick-Less every 4, vertex pruning), ASYNC local moving.
+Workload (default): R-MAT scale 27, edge factor 28 (a/b/c/d = .57/.19/.19/.05,
+seed 27, duplicates and self-loops removed, unit weights, int64 offsets and
+int32 indices; 134M vertices, 7.33G arcs), generated on the device; paper
+defaults (20 iterations, 10 passes, tau 0.01 dropped 10x per pass, tau_agg
+0.8, Pick-Less every 4, vertex pruning), ASYNC local moving.
 
-One step = one complete louvain_run on the device-resident graph.  The
-metric counts stored arcs (each undirected edge twice), as the paper does.
-The timed steps run without per-kernel events; the same number of steps is
-then repeated with HIP events around every launch for the roofline figures.
-Further legs: the degree-bucket autotuner (candidate thresholds timed by
-louvain_autotune, then the workload timed with the winner); the learned
-move-pruner, trained on samples recorded from separate R-MAT graphs (seeds
-1018-1020), with both sweep guards; 4096 batched SBM graphs (ASYNC, SYNC,
-ASYNC with the learned pruner).  Prints one JSON line.
+One step = one complete louvain_run on the device-resident graph.  The metric
+counts stored arcs (each undirected edge twice), as the paper does.  Legs:
+  - plain: warm-up, then exactly --steps timed runs (the headline value);
+  - roofline: event-timed runs (HIP events around every launch, on the
+    handle's stream) give the dominant local-moving kernel's algorithmic
+    bytes and time per launch; the HBM traffic per launch comes from the
+    committed rocprofv3 counter summary of that kernel and workload while
+    its sources are unchanged;
+  - learned: the pruner MLP trained on samples recorded from R-MAT scale
+    18, 19 and 20 graphs (seeds 1018-1020), then timed with the strict sweep
+    guard, the tolerance guard, and threshold 0 with the strict guard (flag
+    pruning plus the same certifying sweeps: isolates what the MLP saves);
+  - autotune: louvain_autotune over candidate degree thresholds;
+  - batch: 4096 SBM graphs, vertex counts log-uniform in [200, 200000];
+  - cpu_baseline: the sequential oracle on the host (one core), and the
+    OpenMP CPU baseline on all host cores with a thread sweep, both on a
+    stated sample of the same recipe when the workload is beyond them.
+Prints one JSON line.
 
-Other workloads (--workload): grid4096, planted, rmatS (S <= 24, edge factor
-16), and rmat27: R-MAT scale 27, edge factor 28, seed 27 (134M vertices,
-about 6.5G arcs, int64 offsets), generated on the device; pass fewer steps
-(e.g. --steps 3 --warmup 1) for it.
+Other workloads (--workload): rmat22, rmatS (S <= 24, edge factor 16),
+grid4096, planted.
 """
 import argparse
 import json
 import os
+import platform
+import statistics
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "Louvain M edges/s, plain vs learned-pruned at ΔQ≤0.002; local-move HBM GB/s"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "move_fused_rmat22_traffic.md")
 TRAFFIC_SOURCES = ["paper_2501_19004_amd/csrc/lv_move.hip", "paper_2501_19004_amd/csrc/lv_common.h",
                    "paper_2501_19004_amd/csrc/lv_internal.h"]
+KERNEL_FILE = {"move_b0_3": "move_fused", "move_b4": "move_lds", "move_hub": "hub"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_digest():
@@ -45,12 +62,13 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
-    or None when the summary is missing or the kernel sources changed since."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when there is none or the sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_FILE.get(kernel, kernel)}_{workload}_traffic.md")
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     vals = {}
@@ -64,6 +82,29 @@ def measured_traffic():
         return int(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def host_info():
+    info = {"cores": os.cpu_count(), "model": platform.processor() or None, "ram_gb": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_gb"] = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    try:
+        info["affinity_cores"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return info
 
 
 def make_graph(name):
@@ -90,119 +131,227 @@ def timed_runs(L, steps, warmup):
         L.run()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / max(steps, 1)
-    q, _, _ = L.modularity()
+    q = L.modularity()[0] if L.count == 0 else None
     return dt, q, L.stats()
 
 
-def learned_leg(lv, torch, nnz, off, idx, w, mode, args, q_plain, dt_plain):
-    """Train the pruner MLP on samples recorded (flag pruning) from R-MAT
-    scale 18 graphs with seeds 1018-1020, then time the workload with it."""
+def roofline_leg(L, runs, workload):
+    """Event-timed runs: per-kernel HIP-event time and algorithmic bytes."""
+    L.set_profiling(True)
+    dtp, _, _ = timed_runs(L, runs, 0)
+    kstats = L.kernel_stats()
+    L.set_profiling(False)
+    moves = [k for k in kstats if k["name"].startswith("move_")]
+    if not moves:
+        return None, kstats
+    dom = max(moves, key=lambda k: k["ms"])
+    ms_launch = dom["ms"] / dom["launches"]
+    bytes_launch = dom["alg_bytes"] / dom["launches"]
+    ach = bytes_launch / (ms_launch * 1e-3) / 1e9
+    tot_ms = sum(k["ms"] for k in moves)
+    tot_b = sum(k["alg_bytes"] for k in moves)
+    traffic = measured_traffic(dom["name"], workload)
+    return {"bound": "hbm", "kernel": dom["name"], "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "traffic_over_algorithmic": round(traffic / bytes_launch, 2) if traffic else None,
+            "event_timed_runs": runs, "event_timed_ms_per_step": round(dtp * 1e3, 3),
+            "launches_per_run": round(dom["launches"] / runs, 1),
+            "avg_launch_us": round(ms_launch * 1e3, 2), "alg_bytes_per_launch": int(bytes_launch),
+            "local_move_phase_GBs": round(tot_b / (tot_ms * 1e-3) / 1e9, 1) if tot_ms else None,
+            "local_move_ms_per_run": round(tot_ms / runs, 3)}, kstats
+
+
+def train_pruner(lv, torch, mode):
+    """Pruner MLP trained on samples recorded (flag pruning) from R-MAT scale
+    18, 19 and 20 graphs, edge factor 16, seeds 1018-1020."""
     import graphgen as gg
     t0 = time.time()
     bufs = []
-    for seed in (1018, 1019, 1020):
-        tg = gg.rmat(18, 16, seed=seed)
+    for scale, seed in ((18, 1018), (19, 1019), (20, 1020)):
+        tg = gg.rmat(scale, 16, seed=seed)
         o2, i2, w2 = lv.graph_tensors(tg, "cuda:0")
         T = lv.Louvain(o2, i2, w2, mode=mode)
-        buf = T.collect_samples(2_000_000, 250)
+        buf = T.collect_samples(4_000_000, 250 >> (scale - 18))
         T.run()
         bufs.append(buf[:T.sample_count()].clone())
         T.close()
+        del buf, o2, i2, w2
     S = torch.cat(bufs)
     pos = float(S[:, 8].mean().item())
     wts = lv.pruner_init(1018, "cuda:0")
     loss0, _ = lv.pruner_loss_grad(wts, S, 1.0)
     loss = lv.pruner_train(wts, S, steps=1500, batch=4096, lr=3e-3, pos_weight=1.0, seed=1018)
     t_train = time.time() - t0
-    print(f"[bench] pruner: {S.shape[0]} samples ({pos:.3f} moved), loss {loss0:.4f} -> {loss:.4f}, "
-          f"{t_train:.1f}s", file=sys.stderr, flush=True)
+    log(f"pruner: {S.shape[0]} samples ({pos:.3f} moved), loss {loss0:.4f} -> {loss:.4f}, {t_train:.1f}s")
+    info = {"graphs": "R-MAT scales 18, 19, 20, edge factor 16, seeds 1018-1020 (250, 125, 62 per mille sampled)",
+            "samples": int(S.shape[0]), "positive_rate": round(pos, 4), "loss_initial": round(loss0, 5),
+            "loss_final": round(loss, 5), "steps": 1500, "batch": 4096, "lr": 3e-3, "seconds": round(t_train, 1)}
+    return wts, info
+
+
+def learned_leg(lv, torch, nnz, graph, mode, args, q_plain, dt_plain, wts, info):
+    off, idx, w = graph
     extra = {} if args.async_coherent is None else {"async_coherent": args.async_coherent}
     legs = {}
-    for guard in ("strict", "tolerance"):
-        L = lv.Louvain(off, idx, w, mode=mode, pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
-                       pruner_threshold=args.threshold, guard_tolerance=1 if guard == "tolerance" else 0, **extra)
-        dt, q, st = timed_runs(L, args.steps, args.warmup)
+    for name, theta, guard in (("strict_guard", args.threshold, 0), ("tolerance_guard", args.threshold, 1),
+                               ("flags_strict_guard", 0.0, 0)):
+        L = lv.Louvain(off, idx, w, mode=mode, pruner=lv.PRUNE_LEARNED, pruner_weights=wts, pruner_threshold=theta,
+                       guard_tolerance=guard, **extra)
+        dt, q, st = timed_runs(L, args.aux_steps, 1)
         L.close()
         del L
         torch.cuda.empty_cache()
-        print(f"[bench] learned ({guard} guard): {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), "
-              f"sweeps={st.sweeps} pruned={st.pruned} iterations={st.iterations}", file=sys.stderr, flush=True)
-        legs[guard] = {"value": round(nnz / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
-                       "speedup_vs_plain": round(dt_plain / dt, 3), "modularity": round(q, 6),
-                       "dq_vs_plain": round(q - q_plain, 6), "equal_modularity": abs(q - q_plain) <= 0.002,
-                       "passes": st.passes, "iterations": st.iterations, "sweeps": st.sweeps, "pruned": st.pruned,
-                       "vertices_evaluated": st.vertices_evaluated, "arcs_scanned": st.arcs_scanned}
-    return wts, {"threshold": args.threshold, "strict_guard": legs["strict"], "tolerance_guard": legs["tolerance"],
-            "training": {"graphs": "R-MAT scale 18, edge factor 16, seeds 1018-1020", "samples": int(S.shape[0]),
-                         "positive_rate": round(pos, 4), "loss_initial": round(loss0, 5), "loss_final": round(loss, 5),
-                         "steps": 1500, "batch": 4096, "lr": 3e-3, "seconds": round(t_train, 1)}}
+        log(f"learned ({name}, theta {theta}): {dt * 1e3:.2f} ms/run, Q={q:.5f} (plain {q_plain:.5f}), "
+            f"sweeps={st.sweeps} pruned={st.pruned} iterations={st.iterations} arcs={st.arcs_scanned}")
+        legs[name] = {"threshold": theta, "value": round(nnz / dt / 1e6, 2), "unit": "M edges/s",
+                      "ms_per_step": round(dt * 1e3, 3), "runs": args.aux_steps,
+                      "speedup_vs_plain": round(dt_plain / dt, 3), "modularity": round(q, 6),
+                      "dq_vs_plain": round(q - q_plain, 6), "equal_modularity": abs(q - q_plain) <= 0.002,
+                      "passes": st.passes, "iterations": st.iterations, "sweeps": st.sweeps, "pruned": st.pruned,
+                      "vertices_evaluated": st.vertices_evaluated, "arcs_scanned": st.arcs_scanned}
+    legs["training"] = info
+    return legs
+
+
+def batch_graphs(count, nmax, threads):
+    """SBM graphs (equal-size communities, 4 to 64 of them, average degree
+    uniform in [8, 32], intra/inter degree ratio 4, weights uniform in
+    [1, 4]) with vertex counts log-uniform in [200, nmax]; graph k uses
+    seed 4000 + k.  Generated by a thread pool (the generators release the
+    interpreter lock)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import graphgen as gg
+    rng = np.random.default_rng(4)
+    specs = []
+    for k in range(count):
+        n = int(np.exp(rng.uniform(np.log(200), np.log(nmax))))
+        specs.append((n, int(rng.integers(4, 65)), float(rng.uniform(8, 32)), 4000 + k))
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda s: gg.sbm_degree(s[0], s[1], s[2], seed=s[3], wmin=1, wmax=4), specs))
 
 
 def batch_leg(lv, torch, args, wts=None):
-    """Batched runs: SBM graphs (equal-size communities, 4 to 64 of them,
-    average degree uniform in [8, 32], intra/inter degree ratio 4, weights
-    uniform in [1, 4]) with vertex counts log-uniform in [200, nmax], graph k
-    generated with seed 4000 + k, all in one batched handle; ASYNC and SYNC
-    plain, and ASYNC with the learned pruner (strict guard) when its weights
-    were trained."""
+    """4096 SBM graphs in one batched handle: ASYNC plain, ASYNC learned
+    (strict guard), and SYNC (the deterministic parity mode, timed for
+    reference: its quality is not Louvain's); per-graph ASYNC quality
+    against the sequential oracle on the first graphs."""
+    import concurrent.futures as cf
+
     import numpy as np
-    import graphgen as gg
     t0 = time.time()
-    rng = np.random.default_rng(4)
-    graphs = []
-    for k in range(args.batch_graphs):
-        n = int(np.exp(rng.uniform(np.log(200), np.log(args.batch_nmax))))
-        graphs.append(gg.sbm_degree(n, int(rng.integers(4, 65)), float(rng.uniform(8, 32)), seed=4000 + k,
-                                    wmin=1, wmax=4))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    graphs = batch_graphs(args.batch_graphs, args.batch_nmax, threads)
     off, idx, w, vbase = lv.batch_tensors(graphs, "cuda:0")
     nv, na = int(vbase[-1]), int(idx.numel())
-    print(f"[bench] batch: {len(graphs)} SBM graphs, {nv} vertices, {na} arcs, built in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    log(f"batch: {len(graphs)} SBM graphs, {nv} vertices, {na} arcs, built in {time.time() - t0:.1f}s")
     out = {"workload": f"{len(graphs)} SBM graphs, vertices log-uniform in [200, {args.batch_nmax}], "
                        f"4-64 communities, average degree U[8,32], intra/inter 4:1, weights U[1,4]",
-           "graphs": len(graphs), "vertices": nv, "arcs": na}
-    legs = [(lv.ASYNC, "async", {}), (lv.SYNC, "sync", {})]
+           "graphs": len(graphs), "vertices": nv, "arcs": na, "offsets": "int64" if off.dtype == torch.int64 else "int32"}
+    legs = [(lv.ASYNC, "async", {})]
     if wts is not None:
         legs.append((lv.ASYNC, "async_learned", dict(pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
                                                      pruner_threshold=args.threshold, guard_tolerance=0)))
+    legs.append((lv.SYNC, "sync_parity_mode", {}))
     qo = None
+    nchk = min(args.batch_check, len(graphs))
     for mode, name, extra in legs:
         L = lv.Louvain(off, idx, w, vbase=vbase, mode=mode, **extra)
-        dt, _, _ = timed_batch(L, args.steps, args.warmup)
+        dt, _, st = timed_runs(L, args.aux_steps, 1)
         q = np.array(L.modularity_batch()[0])
         passes, iters, comms = L.batch_results()
         L.close()
+        del L
+        torch.cuda.empty_cache()
         out[name] = {"value": round(na / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
-                     "mean_modularity": round(float(q.mean()), 6), "max_passes": int(max(passes)),
-                     "max_iterations": int(max(iters))}
+                     "runs": args.aux_steps, "mean_modularity": round(float(q.mean()), 6),
+                     "max_passes": int(max(passes)), "max_iterations": int(max(iters))}
+        if name == "sync_parity_mode":
+            out[name]["note"] = ("SYNC decides every vertex against the iteration's snapshot (bit-exact parity "
+                                 "mode); on these graphs its modularity is far below ASYNC's, so this is a timing "
+                                 "of the parity mode, not a Louvain result")
         if name == "async_learned":
             out[name]["speedup_vs_async"] = round(out["async"]["ms_per_step"] / out[name]["ms_per_step"], 3)
             out[name]["dq_mean_vs_async"] = round(float(q.mean()) - out["async"]["mean_modularity"], 6)
-        if not args.no_cpu_baseline:
-            # quality against the sequential oracle on the first 64 graphs
+        if not args.no_cpu_baseline and mode == lv.ASYNC and nchk:
+            # per-graph quality against the sequential oracle (identity order)
             if qo is None:
                 import oracle
-                qo = []
-                for gk in graphs[:64]:
+
+                def oq(gk):
                     gk.weights = gk.weights.astype(np.int64)
-                    qo.append(oracle.modularity(gk, oracle.louvain(gk).membership))
-            d = [q[k] - qo[k] for k in range(len(qo))]
-            out[name]["dq_vs_oracle_first64"] = {"mean": round(float(np.mean(d)), 6), "min": round(float(min(d)), 6)}
-        print(f"[bench] batch {name}: {dt * 1e3:.2f} ms/run, {na / dt / 1e6:.1f} M arcs/s, mean Q {q.mean():.4f}",
-              file=sys.stderr, flush=True)
+                    return oracle.modularity(gk, oracle.louvain(gk).membership)
+                with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+                    qo = list(ex.map(oq, graphs[:nchk]))
+            d = q[:nchk] - np.array(qo)
+            out[name]["dq_vs_oracle_first_graphs"] = {"graphs": nchk, "mean": round(float(d.mean()), 6),
+                                                      "min": round(float(d.min()), 6),
+                                                      "below_minus_0.002": int((d < -0.002).sum())}
+        log(f"batch {name}: {dt * 1e3:.2f} ms/run, {na / dt / 1e6:.1f} M arcs/s, mean Q {q.mean():.4f}")
+    del off, idx, w
     return out
 
 
-def timed_batch(L, steps, warmup):
-    import torch
-    for _ in range(warmup):
-        L.run()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
-        L.run()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t) / max(steps, 1), None, None
+def cpu_baselines(args, workload_graph, q_gpu):
+    """The sequential oracle (one host core) and the OpenMP CPU baseline (all
+    host cores, plus a thread sweep) on the workload, or on a labelled sample
+    of the same recipe when the workload is beyond the oracle's minutes."""
+    import numpy as np
+
+    import cpu_baseline
+    import graphgen as gg
+    import oracle
+    host = host_info()
+    if workload_graph is not None and workload_graph.nnz <= 200_000_000:
+        gs, label = workload_graph, "the whole workload"
+    else:
+        gs = gg.rmat(21, 28, seed=27)
+        label = f"R-MAT scale 21, edge factor 28, seed 27 ({gs.nnz} arcs; same recipe as the workload)"
+    gs.weights = gs.weights.astype(np.int64)
+    reps = args.cpu_reps
+
+    def runs(fn):
+        fn()  # warm-up
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = fn()
+            ts.append(time.perf_counter() - t)
+        return ts, r
+
+    ts, ref = runs(lambda: oracle.louvain(gs, oracle.Params()))
+    q_or = oracle.modularity(gs, ref.membership)
+    med = statistics.median(ts)
+    cpu = {"value": round(gs.nnz / med / 1e6, 2), "unit": "M edges/s", "cores": 1, "kind": "oracle",
+           "sample": f"{label}; sequential ASYNC oracle, 1 warm-up then median of {reps} runs",
+           "host_cores": host["cores"], "host_cpu": host["model"], "host_ram_gb": host["ram_gb"],
+           "seconds_median": round(med, 3), "seconds_mean": round(statistics.mean(ts), 3),
+           "q_oracle": round(q_or, 6), "note": f"oracle: 1 of {host['cores']} host cores"}
+    if workload_graph is gs and q_gpu is not None:
+        cpu["q_gpu_minus_oracle"] = round(q_gpu - q_or, 6)
+    log(f"oracle on {label}: median {med:.2f}s Q={q_or:.5f} (1 of {host['cores']} cores, {host['model']})")
+    nt = max(1, min(16, host.get("affinity_cores") or host["cores"], cpu_baseline.max_threads()))
+    ts, (memb, st) = runs(lambda: cpu_baseline.louvain(gs, threads=nt))
+    med = statistics.median(ts)
+    q_mc = oracle.modularity(gs, memb)
+    sweep = {}
+    t_one = None
+    for th in sorted({1, 2, 4, 8, 16, nt}):
+        if th > nt:
+            continue
+        t = time.perf_counter()
+        cpu_baseline.louvain(gs, threads=th)
+        sweep[str(th)] = round(time.perf_counter() - t, 3)
+        t_one = sweep["1"] if th == 1 else t_one
+    multi = {"value": round(gs.nnz / med / 1e6, 2), "unit": "M edges/s", "cores": nt,
+             "kind": "openmp-gve-style", "sample": f"{label}; 1 warm-up then median of {reps} runs",
+             "seconds_median": round(med, 3), "modularity": round(q_mc, 6), "passes": st["passes"],
+             "iterations": st["iterations"], "thread_sweep_seconds": sweep,
+             "speedup_all_cores_vs_1": round(t_one / med, 2) if t_one else None}
+    log(f"OpenMP baseline ({nt} threads): median {med:.2f}s Q={q_mc:.5f}; sweep {sweep}")
+    return cpu, multi
 
 
 def main():
@@ -210,8 +359,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--workload", default="rmat27")
     ap.add_argument("--mode", default="async", choices=["async", "sync"])
+    ap.add_argument("--aux-steps", type=int, default=3, help="timed runs of each auxiliary leg (after 1 warm-up)")
+    ap.add_argument("--profile-runs", type=int, default=2, help="event-timed runs for the roofline figures")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="timed CPU-baseline runs (after 1 warm-up)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
@@ -219,18 +371,17 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-SBM leg")
     ap.add_argument("--no-autotune", action="store_true", help="skip the degree-bucket autotuner leg")
     ap.add_argument("--batch-graphs", type=int, default=4096)
-    ap.add_argument("--batch-nmax", type=int, default=20000)
+    ap.add_argument("--batch-nmax", type=int, default=200000)
+    ap.add_argument("--batch-check", type=int, default=64, help="batch graphs checked against the oracle")
     ap.add_argument("--threshold", type=float, default=0.5, help="learned pruner: keep iff sigmoid >= threshold")
-    ap.add_argument("--guard", default="strict", choices=["strict", "tolerance"],
-                    help="learned pruner: a pass ends at a full sweep with no positive-gain move (strict) "
-                         "or whose gain sum passes the tolerance test")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration run) and exit")
     ap.add_argument("--async-coherent", type=int, default=None, choices=[0, 1],
                     help="ASYNC: device-coherent loads of C' and Sigma' (1) or cached loads (0, library default)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the Louvain library runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs the Louvain library on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design, not built)"}))
         sys.exit(2)
 
     import numpy as np
@@ -252,7 +403,7 @@ def main():
         return
     t0 = time.time()
     if args.workload == "rmat27":
-        # 134M vertices, ~6.5G arcs: built and kept on the device only
+        # 134M vertices, 7.33G arcs: built and kept on the device only
         import graphgen as gg
         g = None
         off, idx = gg.rmat_device(27, 28, seed=27, device="cuda:0")
@@ -266,101 +417,58 @@ def main():
         g, desc = make_graph(args.workload)
         off, idx, w = lv.graph_tensors(g, "cuda:0")
         n, nnz = g.n, g.nnz
-    print(f"[bench] generated {desc}: n={n} arcs={nnz} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    log(f"generated {desc}: n={n} arcs={nnz} in {time.time() - t0:.1f}s")
     mode = lv.ASYNC if args.mode == "async" else lv.SYNC
     extra = {} if args.async_coherent is None else {"async_coherent": args.async_coherent}
     L = lv.Louvain(off, idx, w, mode=mode, **extra)
     dt, q, st = timed_runs(L, args.steps, args.warmup)
-    print(f"[bench] {args.steps} runs, {dt * 1e3:.2f} ms/run, Q={q:.5f}, passes={st.passes} "
-          f"iterations={st.iterations} communities={st.communities}", file=sys.stderr, flush=True)
-    kstats = []
-    if not args.no_profile:
-        L.set_profiling(True)
-        dtp, _, _ = timed_runs(L, args.steps, 0)
-        kstats = L.kernel_stats()
-        L.set_profiling(False)
-        print(f"[bench] {args.steps} event-timed runs, {dtp * 1e3:.2f} ms/run", file=sys.stderr, flush=True)
-
+    log(f"{args.steps} runs, {dt * 1e3:.2f} ms/run, Q={q:.5f}, passes={st.passes} iterations={st.iterations} "
+        f"communities={st.communities}")
     roofline = None
-    if kstats:
+    if not args.no_profile:
+        roofline, kstats = roofline_leg(L, args.profile_runs, args.workload)
         if args.kernels:
             for k in kstats:
                 gbs = k["alg_bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 and k["alg_bytes"] else 0.0
-                print(f"[kernel] {k['name']:16s} launches={k['launches']:6d} ms={k['ms']:9.3f} "
+                print(f"[kernel] {k['name']:22s} launches={k['launches']:6d} ms={k['ms']:9.3f} "
                       f"alg_GB={k['alg_bytes'] / 1e9:8.3f} GB/s={gbs:8.1f}", file=sys.stderr)
-        moves = [k for k in kstats if k["name"].startswith("move_")]
-        if moves:
-            dom = max(moves, key=lambda k: k["ms"])
-            ms_launch = dom["ms"] / dom["launches"]
-            bytes_launch = dom["alg_bytes"] / dom["launches"]
-            ach = bytes_launch / (ms_launch * 1e-3) / 1e9
-            tot_ms = sum(k["ms"] for k in moves)
-            tot_b = sum(k["alg_bytes"] for k in moves)
-            roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
-                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
-                        "traffic": (measured_traffic() if dom["name"] == "move_b0_3" and args.workload == "rmat22"
-                                    and args.mode == "async" else None),
-                        "event_timed_ms_per_step": round(dtp * 1e3, 3),
-                        "avg_launch_us": round(ms_launch * 1e3, 2),
-                        "alg_bytes_per_launch": int(bytes_launch),
-                        "local_move_phase_GBs": round(tot_b / (tot_ms * 1e-3) / 1e9, 1) if tot_ms else None,
-                        "local_move_ms_per_run": round(tot_ms / args.steps, 3)}
-
-    plain_params = (L.params.async_coherent, L.params.async_min_label)
+        if roofline:
+            log(f"roofline: {roofline['kernel']} {roofline['achieved']} GB/s ({roofline['frac']:.3f} of peak), "
+                f"{roofline['avg_launch_us']} us/launch")
+    plain_params = (L.params.async_coherent, L.params.async_min_label, L.params.async_slices)
     tuned = None
     if not args.no_autotune:
-        # degree-bucket autotuner: candidate move-bucket thresholds, 2 timed runs each
-        cands = [[8, 32, 128, 512, 4096], [8, 32, 128, 1024, 4096], [8, 16, 64, 256, 4096], [4, 16, 64, 512, 4096],
-                 [8, 32, 64, 256, 2048], [16, 32, 128, 512, 4096]]
-        t0 = time.time()
-        best, cms = L.autotune(cands, reps=2)
-        dtt, qt, stt = timed_runs(L, args.steps, args.warmup)
-        tuned = {"candidates": cands, "candidate_ms": [round(x, 3) for x in cms], "best": best,
-                 "bucket_max_degree": cands[best], "value": round(nnz / dtt / 1e6, 2), "unit": "M edges/s",
-                 "ms_per_step": round(dtt * 1e3, 3), "modularity": round(qt, 6),
-                 "speedup_vs_defaults": round(dt / dtt, 3), "tuning_seconds": round(time.time() - t0 - dtt * (args.steps + args.warmup), 1)}
-        print(f"[bench] autotuned buckets {cands[best]}: {dtt * 1e3:.2f} ms/run, Q={qt:.5f} "
-              f"(candidates {[round(x, 2) for x in cms]} ms)", file=sys.stderr, flush=True)
+        cands = ([[8, 32, 128, 1024, 4096], [8, 32, 128, 512, 8192]] if args.workload == "rmat27" else
+                 [[8, 32, 128, 1024, 4096], [8, 16, 64, 256, 4096], [4, 16, 64, 512, 4096], [16, 32, 128, 512, 4096]])
+        reps = 2 if args.workload == "rmat27" else 3
+        t1 = time.time()
+        best, cms = L.autotune(cands, reps=reps)
+        dtt, qt, _ = timed_runs(L, args.aux_steps, 0)
+        tuned = {"candidates": cands, "candidate_ms": [round(x, 3) for x in cms], "reps": reps, "best": best,
+                 "kept": "defaults" if best < 0 else cands[best], "value": round(nnz / dtt / 1e6, 2),
+                 "unit": "M edges/s", "ms_per_step": round(dtt * 1e3, 3), "modularity": round(qt, 6),
+                 "speedup_vs_defaults": round(dt / dtt, 3), "tuning_seconds": round(time.time() - t1, 1)}
+        log(f"autotune kept {tuned['kept']}: {dtt * 1e3:.2f} ms/run, Q={qt:.5f} (candidates "
+            f"{[round(x, 2) for x in cms]} ms)")
     L.close()
     del L
     torch.cuda.empty_cache()
     learned = wts = None
     if not args.no_learned:
-        wts, learned = learned_leg(lv, torch, nnz, off, idx, w, mode, args, q, dt)
+        wts, info = train_pruner(lv, torch, mode)
+        learned = learned_leg(lv, torch, nnz, (off, idx, w), mode, args, q, dt, wts, info)
+    if g is None:
+        del off, idx, w
+        torch.cuda.empty_cache()
     batch = None
     if not args.no_batch:
         batch = batch_leg(lv, torch, args, wts)
-
-    cpu = None
+    cpu = multicore = None
     if not args.no_cpu_baseline:
-        import oracle
-        cores = 1
-        if g is not None:
-            g.weights = g.weights.astype(np.int64)
-            t = time.perf_counter()
-            ref = oracle.louvain(g, oracle.Params())
-            tc = time.perf_counter() - t
-            q_or = oracle.modularity(g, ref.membership)
-            cpu = {"value": round(g.nnz / tc / 1e6, 2), "unit": "M edges/s", "cores": cores, "kind": "oracle",
-                   "sample": f"whole workload, sequential ASYNC oracle, one run ({tc:.1f} s)",
-                   "q_oracle": round(q_or, 6), "q_gpu_minus_oracle": round(q - q_or, 6)}
-            print(f"[bench] oracle {tc:.1f}s Q={q_or:.5f} (gpu-oracle {q - q_or:+.5f})", file=sys.stderr, flush=True)
-        else:
-            # the full graph is far beyond the oracle's reach: time it on a
-            # smaller R-MAT of the same recipe and report its arc rate
-            import graphgen as gg
-            gs = gg.rmat(21, 28, seed=27)
-            gs.weights = gs.weights.astype(np.int64)
-            t = time.perf_counter()
-            ref = oracle.louvain(gs, oracle.Params())
-            tc = time.perf_counter() - t
-            cpu = {"value": round(gs.nnz / tc / 1e6, 2), "unit": "M edges/s", "cores": cores, "kind": "oracle",
-                   "sample": (f"R-MAT scale 21, edge factor 28, seed 27 ({gs.nnz} arcs), sequential ASYNC oracle, "
-                              f"one run ({tc:.1f} s)")}
-            print(f"[bench] oracle on R-MAT 21/28: {tc:.1f}s", file=sys.stderr, flush=True)
+        cpu, multicore = cpu_baselines(args, g, q)
 
     out = {
-        "metric": "Louvain M edges/s (plain, ASYNC, paper defaults)",
+        "metric": METRIC,
         "value": round(nnz / dt / 1e6, 2),
         "unit": "M edges/s",
         "n_gpus": 1,
@@ -374,14 +482,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "vertices": n, "arcs": nnz, "undirected_edges": nnz // 2,
                    "mode": args.mode, "pruner": "flags", "async_coherent": plain_params[0],
-                   "async_min_label": plain_params[1], "modularity": round(q, 6), "passes": st.passes,
-                   "iterations": st.iterations, "communities": st.communities,
+                   "async_min_label": plain_params[1], "async_slices": plain_params[2], "modularity": round(q, 6),
+                   "passes": st.passes, "iterations": st.iterations, "communities": st.communities,
                    "vertices_evaluated": st.vertices_evaluated, "arcs_scanned": st.arcs_scanned,
-                   "undirected_Medges_per_s": round(nnz / 2 / dt / 1e6, 2)},
+                   "undirected_Medges_per_s": round(nnz / 2 / dt / 1e6, 2),
+                   "paper_context": "GVE-Louvain 560 M edges/s on sk-2005 (3.80G arcs), 2x Xeon Gold 6226R (32 "
+                                    "cores); nu-Louvain 405 M edges/s on it-2004 (2.19G arcs), A100; other graphs "
+                                    "and hardware, float32 weights"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "autotuned": tuned,
+        "cpu_baseline_multicore": multicore,
         "learned_pruner": learned,
+        "autotuned": tuned,
         "batch": batch,
     }
     print(json.dumps(out))
