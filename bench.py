@@ -214,23 +214,17 @@ def learned_leg(lv, torch, nnz, graph, mode, args, q_plain, dt_plain, wts, info)
 
 
 def batch_graphs(count, nmax, threads):
-    """SBM graphs (equal-size communities, 4 to 64 of them, average degree
-    uniform in [8, 32], intra/inter degree ratio 4, weights uniform in
-    [1, 4]) with vertex counts log-uniform in [200, nmax]; graph k uses
-    seed 4000 + k.  Generated by a thread pool (the generators release the
-    interpreter lock)."""
+    """SBM graphs of graphgen.sbm_batch_specs (equal-size communities, 4 to
+    64 of them, average degree uniform in [8, 32], intra/inter degree ratio
+    4, weights uniform in [1, 4], vertex counts log-uniform in [200, nmax],
+    graph k seeded 4000 + k), generated by a thread pool (the generators
+    release the interpreter lock)."""
     import concurrent.futures as cf
 
-    import numpy as np
-
     import graphgen as gg
-    rng = np.random.default_rng(4)
-    specs = []
-    for k in range(count):
-        n = int(np.exp(rng.uniform(np.log(200), np.log(nmax))))
-        specs.append((n, int(rng.integers(4, 65)), float(rng.uniform(8, 32)), 4000 + k))
+    specs = gg.sbm_batch_specs(count, nmax)
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        return list(ex.map(lambda s: gg.sbm_degree(s[0], s[1], s[2], seed=s[3], wmin=1, wmax=4), specs))
+        return list(ex.map(gg.sbm_batch_graph, specs))
 
 
 def batch_leg(lv, torch, args, wts=None):

@@ -350,6 +350,25 @@ def sbm_degree(n: int, k: int, avg_degree: float, ratio: float = 4.0, seed: int 
     return g
 
 
+def sbm_batch_specs(count: int, nmax: int = 200_000, nmin: int = 200, seed: int = 4):
+    """Recipe of the batched SBM workload: for graph k, (n, communities,
+    average degree, seed) with n log-uniform in [nmin, nmax], 4 to 64
+    communities, average degree uniform in [8, 32] and seed 4000 + k (drawn in
+    order from numpy's default generator seeded with `seed`)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k in range(count):
+        n = int(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
+        specs.append((n, int(rng.integers(4, 65)), float(rng.uniform(8, 32)), 4000 + k))
+    return specs
+
+
+def sbm_batch_graph(spec) -> CSRGraph:
+    """One graph of sbm_batch_specs: intra/inter degree ratio 4, weights in [1, 4]."""
+    n, k, d, s = spec
+    return sbm_degree(n, k, d, seed=s, wmin=1, wmax=4)
+
+
 def erdos(n: int, p: float, seed: int = 7, wmin: int = 1, wmax: int = 1) -> CSRGraph:
     cap = n * (n - 1) // 2 + 1
     keys = np.empty(cap, dtype=np.uint64)

@@ -489,17 +489,17 @@ class Louvain:
             pass
 
 
-def batch_tensors(graphs, device="cuda", unit_weights: bool | None = None):
+def batch_tensors(graphs, device="cuda", unit_weights: bool | None = None, offset_bits: int | None = None):
     """Lay graphgen.CSRGraphs end to end: returns (offsets, indices, weights-or-None,
     vbase) for Louvain(..., vbase=vbase).  Offsets are int64 when the union has
-    2^31 or more arcs."""
+    2^31 or more arcs or offset_bits is 64."""
     import numpy as np
     import torch
     ns = [g.n for g in graphs]
     ms = [int(g.offsets[-1]) for g in graphs]
     vbase = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
     ebase = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
-    big = ebase[-1] > 0x7fffffff
+    big = ebase[-1] > 0x7fffffff or offset_bits == 64
     off = np.empty(vbase[-1] + 1, dtype=np.int64)
     off[-1] = ebase[-1]
     idx = np.empty(ebase[-1], dtype=np.int32)

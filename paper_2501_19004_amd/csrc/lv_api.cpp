@@ -637,7 +637,7 @@ louvain_status Runner::run() {
     u64* Sg_dev = batch ? at<u64>(Y.Sg) : nullptr;
     u64* Pg_dev = batch && learned ? at<u64>(Y.Pg) : nullptr;
     u64* gcnt_dev = batch ? at<u64>(Y.gcnt) : nullptr;
-    std::vector<uint8_t> alive(nbg, 1), act(nbg, 0), ran(nbg, 0);
+    std::vector<uint8_t> alive(nbg, 1), act(nbg, 0), ran(nbg, 0), due(nbg, 1);
     std::vector<int32_t> li_g(nbg, 0);
     std::vector<int64_t> nver(nbg, 0);
     std::vector<u64> hS(2 * nbg), hcnt(2 * nbg), hP(nbg);
@@ -671,6 +671,7 @@ louvain_status Runner::run() {
             for (int64_t g = 0; g < nbg; g++) {
                 act[g] = ran[g] = alive[g];
                 li_g[g] = P.max_iterations;
+                due[g] = 1;  // iteration 0 of a pass is every graph's sweep
             }
             if ((st = upload_act()) != LOUVAIN_OK) return st;
             HIPCHK(H, hipMemsetAsync(gcnt_dev, 0, (size_t)nbg * 16, s));
@@ -1013,19 +1014,25 @@ louvain_status Runner::run() {
                 // test passes in that graph (no evaluation with a positive best
                 // gain, or the tolerance test); sweeps are taken by all graphs
                 // together, after a non-sweep iteration where any graph passed
-                // the tolerance test or when the filter kept nothing
+                // the tolerance test or when the filter kept nothing.  The strict
+                // test is exact whoever asked for the sweep; the tolerance test
+                // ends a graph's pass only at a sweep that graph asked for itself
+                // (iteration 0, its own tolerance pass, or an empty filter), so
+                // its pass ends where it would end in a lone run's schedule.
                 bool changed = false, any = false, want_sweep = false;
                 for (int64_t g = 0; g < nbg; g++) {
                     if (!act[g]) continue;
                     const unsigned __int128 Sg = ((unsigned __int128)hS[2 * g + 1] << 64) + hS[2 * g];
                     const bool conv_g = may_end && converged(Sg, (int64_t)H->Wg[g], P, pass);
-                    if (sweep && (P.guard_tolerance ? conv_g : hP[g] == 0)) {
+                    const bool exit_g = P.guard_tolerance ? (due[g] && conv_g) : hP[g] == 0;
+                    if (sweep && exit_g) {
                         li_g[g] = t + 1;
                         act[g] = 0;
                         changed = true;
                     } else {
                         any = true;
-                        if (!sweep && conv_g) want_sweep = true;
+                        due[g] = !sweep && conv_g;
+                        if (due[g]) want_sweep = true;
                     }
                 }
                 if (!any) { li = t + 1; break; }
@@ -1037,6 +1044,7 @@ louvain_status Runner::run() {
                     if ((st = filter_next(t, stamp_next, fnext, qnext, &it, &kept)) != LOUVAIN_OK) return st;
                     if (kept == 0) {
                         next_sweep = true;
+                        std::fill(due.begin(), due.end(), (uint8_t)1);  // every graph needs the certifying sweep
                     } else {
                         H->st.pruned += (int64_t)hc->pruned;
                         csegs[0] = 0;

@@ -417,7 +417,25 @@ struct MoveShm {
     int32_t gi[32];
     int32_t ncl[32];  // occupied slots listed per group
     i64 arcs[32], nd[32];
+    u64 wsum[256 / WAVE][9];  // lane path: per-wave partial block totals
 };
+
+// Queue entry of work slot `slot` of a launch: the slot-th entry of the
+// launch's list (strided for interleaved slices), or, for batched ASYNC
+// slices, the entry of the slot's graph segment.
+__device__ __forceinline__ int64_t queue_entry(const MoveArgs& a, int64_t slot) {
+    int64_t e = slot * a.lstride + a.lphase;
+    if (a.seg_pre) {
+        int32_t lo = 0, hi = a.seg_n - 1;  // graph of this slot: largest g with seg_pre[g] <= slot
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (a.seg_pre[mid] <= slot) lo = mid; else hi = mid - 1;
+        }
+        const int64_t len = a.seg_cnt[lo];
+        e = a.seg_start[lo] + len * a.seg_k / a.seg_ns + (slot - a.seg_pre[lo]);
+    }
+    return e;
+}
 
 // One block of a degree bucket: NG = BLOCK/G vertices, each evaluated by G
 // lanes with a CAP-slot table in LDS (keys/vals point at this block's LDS).
@@ -437,20 +455,7 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t slot = blk * NG + grp;
     const bool listed = slot < count;
-    int32_t i = -1;
-    if (listed) {
-        int64_t e = slot * a.lstride + a.lphase;
-        if (a.seg_pre) {
-            int32_t lo = 0, hi = a.seg_n - 1;  // graph of this slot: largest g with seg_pre[g] <= slot
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (a.seg_pre[mid] <= slot) lo = mid; else hi = mid - 1;
-            }
-            const int64_t len = a.seg_cnt[lo];
-            e = a.seg_start[lo] + len * a.seg_k / a.seg_ns + (slot - a.seg_pre[lo]);
-        }
-        i = list[e];
-    }
+    const int32_t i = listed ? list[queue_entry(a, slot)] : -1;
     const int32_t gi = (listed && a.gid) ? a.gid[i] : -1;  // batched runs: graph of i
     const bool active = listed && (gi < 0 || a.gact[gi]);
     const i64 Wi = gi >= 0 ? (i64)a.Wg[gi] : a.W;
@@ -607,6 +612,114 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     }
 }
 
+// Bucket 0: one vertex per lane, 256 per block.  A row of at most D = LANE_DEG
+// arcs stays in registers: K_{i->d} of each distinct neighbour community is
+// the sum over the row's entries of that community, found by comparing the
+// entries pairwise (D^2 register compares, no table, no barrier), and the
+// Sigma of each distinct candidate is gathered once.  The decision rule is the
+// groups' (finish_decision), so both paths pick the same community.
+constexpr int LANE_DEG = MOVE_CAP[0] / 2;
+
+template <typename OffT, int WK, int MODE, typename KeyT>
+__device__ __forceinline__ void move_lanes(const MoveArgs& a, const int32_t* __restrict__ list, int32_t count,
+                                           int64_t blk, int bucket, MoveShm& sh) {
+    constexpr int D = LANE_DEG;
+    const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
+    const int64_t slot = blk * 256 + threadIdx.x;
+    const bool listed = slot < count;
+    const int32_t i = listed ? list[queue_entry(a, slot)] : -1;
+    const int32_t gi = (listed && a.gid) ? a.gid[i] : -1;  // batched runs: graph of i
+    const bool active = listed && (gi < 0 || a.gact[gi]);
+    const i64 Wi = gi >= 0 ? (i64)a.Wg[gi] : a.W;
+    int32_t c = 0;
+    i64 Ki = 0, o0 = 0, Sc = 0;
+    int deg = 0;
+    if (active) {
+        c = ld_c<MODE>(&a.Cp[i]);
+        Ki = a.K[i];
+        o0 = (i64)g.off[i];
+        deg = (int)((i64)g.off[i + 1] - o0);
+        Sc = ld_s<MODE>(&a.Sig[c]);  // in flight while the row is read
+    }
+    int32_t jj[D], dd[D];
+    i64 ww[D];
+#pragma unroll
+    for (int u = 0; u < D; u++) {
+        jj[u] = u < deg ? g.idx[o0 + u] : i;
+        ww[u] = u < deg ? g.weight(o0 + u) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < D; u++) dd[u] = jj[u] != i ? ld_c<MODE>(&a.Cp[jj[u]]) : EMPTY_KEY;
+    // kd[u]: weight from i to community dd[u]; first[u]: u is that community's first entry
+    i64 kd[D];
+    bool first[D];
+#pragma unroll
+    for (int u = 0; u < D; u++) {
+        i64 sum = 0;
+        bool f = dd[u] != EMPTY_KEY;
+#pragma unroll
+        for (int v = 0; v < D; v++) {
+            const bool same = dd[v] == dd[u];
+            sum += same ? ww[v] : 0;
+            if (v < u && same) f = false;
+        }
+        kd[u] = sum;
+        first[u] = f;
+    }
+    i64 kic = 0, nd = 0;
+#pragma unroll
+    for (int u = 0; u < D; u++) {
+        nd += first[u] ? 1 : 0;
+        if (first[u] && dd[u] == c) kic = kd[u];
+    }
+    i64 sd[D];
+#pragma unroll
+    for (int u = 0; u < D; u++) sd[u] = (first[u] && dd[u] != c) ? ld_s<MODE>(&a.Sig[dd[u]]) : 0;
+    KeyT bk = 0;
+    int32_t bd = EMPTY_KEY;
+    i64 bv = 0;
+#pragma unroll
+    for (int u = 0; u < D; u++) {
+        if (!first[u] || dd[u] == c) continue;
+        const KeyT key = (KeyT)Wi * kd[u] - (KeyT)Ki * sd[u];
+        if (bd == EMPTY_KEY || better(key, dd[u], bk, bd)) { bk = key; bd = dd[u]; bv = kd[u]; }
+    }
+    Decision dcs = finish_decision<MODE, KeyT>(a, Wi, active, c, Ki, Best<KeyT>{bk, bd, bv, kic, nd}, Sc);
+
+    if (a.learn && active) note_evaluation(a, i, dcs);
+    if constexpr (MODE == M_SYNC) {
+        if (listed) a.sdec[i] = dcs.target;  // -1 for a vertex of a graph that has converged
+    } else if (dcs.target >= 0 && apply_async<MODE>(a, Wi, i, c, Ki, dcs) && (a.prune || a.learn)) {
+#pragma unroll
+        for (int u = 0; u < D; u++)
+            if (u < deg) mark_one(a, i, jj[u]);
+    }
+    // batched runs: per-graph gain sums and positive-gain counts, per lane
+    if (a.Sg && active && dcs.target >= 0 && dcs.gain != 0)
+        atomic_add_i128(&a.Sg[2 * gi], &a.Sg[2 * gi + 1], dcs.gain);
+    if (a.Pg && active && dcs.positive) atomicAdd(&a.Pg[gi], 1ull);
+    // block totals: wave sums, then one lane adds the block's
+    const bool moved = active && dcs.target >= 0;
+    const Split128 sp = moved ? split128(dcs.gain) : Split128{0, 0, 0};
+    u64 v9[9] = {active ? 1ull : 0ull, active ? (u64)deg : 0ull, active ? (u64)nd : 0ull, moved ? 1ull : 0ull,
+                 moved ? (u64)deg : 0ull, (active && dcs.positive) ? 1ull : 0ull, sp.lo, sp.mid, sp.hi};
+    const int w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int q = 0; q < 9; q++) v9[q] = (u64)group_sum64<WAVE>((i64)v9[q]);
+    if (threadIdx.x % WAVE == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; q++) sh.wsum[w][q] = v9[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 t[9] = {};
+        for (int k = 0; k < 256 / WAVE; k++)
+#pragma unroll
+            for (int q = 0; q < 9; q++) t[q] += sh.wsum[k][q];
+        add_block_totals_split(a.ctl, bucket, t[0], t[1], t[2], t[3], t[4], Split128{t[6], t[7], t[8]}, t[5]);
+    }
+}
+
 template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE>
 __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, const int32_t* __restrict__ list,
                                                                 int32_t count) {
@@ -635,11 +748,9 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
     aa.seg_cnt = f.seg_cnt[bk];
     switch (bk) {
         case 0: {
-            constexpr int NG = 256 / MOVE_G[0];
-            constexpr int TB = NG * MOVE_CAP[0];
-            move_block<OffT, WK, AccT, MOVE_G[0], MOVE_CAP[0], MODE>(
-                aa, f.list[0], f.count[0], blk, 0, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
-                (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
+            static_assert(MOVE_G[0] == 1, "bucket 0 is the lane-per-vertex path");
+            if (!aa.wide) move_lanes<OffT, WK, MODE, i64>(aa, f.list[0], f.count[0], blk, 0, sh);
+            else move_lanes<OffT, WK, MODE, i128>(aa, f.list[0], f.count[0], blk, 0, sh);
             break;
         }
         case 1: {
@@ -1104,7 +1215,7 @@ void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const Fu
         constexpr int WK = decltype(w)::value;
         using AccT = typename decltype(ac)::type;
         size_t shm = 0;
-        for (int b = 0; b < 4; b++)
+        for (int b = 1; b < 4; b++)  // bucket 0 (one vertex per lane) has no table
             shm = std::max(shm, (size_t)(256 / MOVE_G[b]) * MOVE_CAP[b] * (4 + sizeof(AccT) + 1));
         if (mode == M_SYNC) k_move_fused<OffT, WK, AccT, M_SYNC><<<(unsigned)grid, 256, shm, s>>>(a, f);
         else if (mode == M_ASYNC_CACHED) k_move_fused<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)grid, 256, shm, s>>>(a, f);

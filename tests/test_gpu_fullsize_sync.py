@@ -1,0 +1,104 @@
+"""Full-size SYNC parity against stored oracle results.
+
+The sequential oracle needs minutes on these graphs, so its results were
+computed once by tests/golden/make_full_size.py (oracle and seeded generators
+only) and stored as SHA-256 digests of little-endian arrays.  The GPU run
+must reproduce them exactly:
+
+* R-MAT scale 22, edge factor 16 (hubs, the workgroup bucket, big-community
+  aggregation at scale): per iteration the moves, the exact gain sum, C' and
+  Sigma'; per pass the super-graph CSR; the final membership, pass and
+  iteration counts and the exact modularity.
+* A sample of the batched SBM recipe over its whole vertex range [200,
+  200000] (its four largest graphs and every 128th one), batched with 64-bit
+  offsets: each graph's membership, passes, iterations, communities and
+  exact modularity equal its lone oracle run.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lv = pytest.importorskip("paper_2501_19004_amd")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+def sha(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).astype(a.dtype.newbyteorder("<"), copy=False).tobytes())
+    return h.hexdigest()
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def test_full_size_sync_rmat22_every_iteration():
+    ref = load("rmat22_sync.json")
+    g = gg.rmat(22, 16, seed=22)
+    assert (g.n, g.nnz) == (ref["n"], ref["nnz"])
+    assert sha(np.asarray(g.offsets, np.int64), np.asarray(g.indices, np.int32)) == ref["graph_sha256"]
+    print("[case] R-MAT 22 SYNC full run with per-iteration digests", flush=True)
+    off, idx, w = lv.graph_tensors(g, dev())
+    L = lv.Louvain(off, idx, w, mode=lv.SYNC)
+    iters, graphs = [], []
+    L.trace(lambda p, t, cp, sig, m, gain: iters.append((p, t, m, gain, sha(cp.astype(np.int32)),
+                                                         sha(sig.astype(np.int64)))),
+            lambda p, n, o, i, ww, it: graphs.append((n, int(o[-1]), sha(o.astype(np.int64), i.astype(np.int32),
+                                                                          ww.astype(np.int64)))))
+    L.run()
+    memb = L.membership().cpu().numpy()
+    q, num, den = L.modularity()
+    st = L.stats()
+    L.close()
+    assert len(iters) == len(ref["iters"])
+    for a, b in zip(iters, ref["iters"]):
+        where = f"pass {b['pass']} iter {b['iter']}"
+        assert (a[0], a[1]) == (b["pass"], b["iter"]), where
+        assert (a[2], a[3]) == (b["moves"], int(b["gain"])), where
+        assert a[4] == b["cprime_sha256"], where
+        assert a[5] == b["sigma_sha256"], where
+    assert [(x[0], x[1], x[2]) for x in graphs] == [(b["n"], b["nnz"], b["csr_sha256"]) for b in ref["graphs"]]
+    assert (st.passes, st.iterations, st.communities) == (ref["passes"], ref["iterations"], ref["communities"])
+    assert sha(memb.astype(np.int32)) == ref["membership_sha256"]
+    assert (num, den) == (int(ref["q_num"]), int(ref["q_den"]))
+
+
+def test_full_range_sbm_batch_sync_per_graph():
+    ref = load("sbm_fullrange_sync.json")["graphs"]
+    specs = gg.sbm_batch_specs(4096, 200_000)
+    graphs = [gg.sbm_batch_graph(specs[r["index"]]) for r in ref]
+    for g, r in zip(graphs, ref):
+        assert sha(np.asarray(g.offsets, np.int64), np.asarray(g.indices, np.int32),
+                   np.asarray(g.weights, np.int32)) == r["graph_sha256"], r["index"]
+    print(f"[case] batched SYNC over {len(graphs)} graphs of the full-range SBM recipe, 64-bit offsets", flush=True)
+    off, idx, w, vbase = lv.batch_tensors(graphs, dev(), offset_bits=64)
+    assert off.dtype == torch.int64
+    L = lv.Louvain(off, idx, w, vbase=vbase, mode=lv.SYNC)
+    L.run()
+    memb = L.membership().cpu().numpy()
+    q, num, den = L.modularity_batch()
+    passes, iters, comms = L.batch_results()
+    L.close()
+    for k, r in enumerate(ref):
+        part = memb[vbase[k]:vbase[k + 1]]
+        where = (k, r["index"], r["n"])
+        assert sha(part.astype(np.int32)) == r["membership_sha256"], where
+        assert (passes[k], iters[k], comms[k]) == (r["passes"], r["iterations"], r["communities"]), where
+        assert (num[k], den[k]) == (int(r["q_num"]), int(r["q_den"])), where
