@@ -350,6 +350,23 @@ louvain_status louvain_pruner_train(float* weights, const float* samples, int64_
                                     int32_t batch, float lr, float pos_weight, uint64_t seed, float* scratch,
                                     double* last_loss, void* stream);
 
+/* louvain_pruner_train without caller scratch and without any device
+ * allocation, for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and errors as louvain_pruner_train, minus `scratch`: the gradient,
+ * Adam moments and loss accumulator live in a static device array of
+ * LOUVAIN_NOALLOC_SCRATCH_FLOATS floats (32 KiB), one per GPU, held until the
+ * process ends.  Runs on the current device; `stream` must belong to it
+ * (LOUVAIN_ERR_INVALID otherwise).  LOUVAIN_ERR_INVALID when
+ * louvain_pruner_scratch_floats(batch) exceeds the array.  Every call on a
+ * GPU shares that GPU's array (each call clears what it needs at its start):
+ * calls that overlap on one GPU, on any streams, race and give undefined
+ * weights. */
+#define LOUVAIN_NOALLOC_SCRATCH_FLOATS 8192
+louvain_status louvain_pruner_train_noalloc(float* weights, const float* samples, int64_t count, int32_t steps,
+                                            int32_t batch, float lr, float pos_weight, uint64_t seed,
+                                            double* last_loss, void* stream);
+
 /* Last error message of h (or of the last failed create when h is NULL).
  * Never NULL; valid until the next call on h. */
 const char* louvain_last_error(const louvain_t* h);

@@ -35,7 +35,8 @@ EXPORTED = ["louvain_params_default", "louvain_workspace_size", "louvain_create"
             "louvain_collect_samples", "louvain_sample_count", "louvain_pruner_init", "louvain_pruner_predict",
             "louvain_pruner_loss_grad", "louvain_pruner_scratch_floats", "louvain_pruner_train",
             "louvain_workspace_size_batch", "louvain_create_batch", "louvain_modularity_batch",
-            "louvain_batch_results", "louvain_autotune"]
+            "louvain_batch_results", "louvain_autotune", "louvain_pruner_train_noalloc"]
+NOALLOC_SCRATCH_FLOATS = 8192
 
 
 class LouvainGraph(ctypes.Structure):
@@ -145,6 +146,10 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_pruner_train.restype = ctypes.c_int
     lib.louvain_pruner_train.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                          ctypes.c_float, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.louvain_pruner_train_noalloc.restype = ctypes.c_int
+    lib.louvain_pruner_train_noalloc.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_float, ctypes.c_float, ctypes.c_uint64,
+                                                 ctypes.POINTER(ctypes.c_double), vp]
     _lib = lib
     return lib
 
@@ -300,6 +305,14 @@ def louvain_pruner_train(weights_ptr: int, samples_ptr: int, count: int, steps: 
     loss = ctypes.c_double()
     _check(load_library().louvain_pruner_train(weights_ptr, samples_ptr, count, steps, batch, lr, pos_weight, seed,
                                                scratch_ptr, ctypes.byref(loss), stream))
+    return float(loss.value)
+
+
+def louvain_pruner_train_noalloc(weights_ptr: int, samples_ptr: int, count: int, steps: int, batch: int, lr: float,
+                                 pos_weight: float, seed: int, stream: int) -> float:
+    loss = ctypes.c_double()
+    _check(load_library().louvain_pruner_train_noalloc(weights_ptr, samples_ptr, count, steps, batch, lr, pos_weight,
+                                                       seed, ctypes.byref(loss), stream))
     return float(loss.value)
 
 

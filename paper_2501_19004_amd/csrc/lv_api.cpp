@@ -1715,12 +1715,15 @@ louvain_status louvain_pruner_loss_grad(const float* weights, const float* sampl
     return LOUVAIN_OK;
 }
 
-louvain_status louvain_pruner_train(float* weights, const float* samples, int64_t count, int32_t steps,
-                                    int32_t batch, float lr, float pos_weight, uint64_t seed, float* scratch,
-                                    double* last_loss, void* stream) {
-    if (!weights || !scratch || count <= 0 || !samples || steps < 0 || batch <= 0)
-        return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid arguments (need samples, count > 0, batch > 0)");
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+// Adam training with the gradient, the two moments and the loss accumulator
+// in `scratch` (louvain_pruner_scratch_floats floats); every part that must
+// start at zero is cleared here, on the stream, before it is used.
+louvain_status train_with_scratch(float* weights, const float* samples, int64_t count, int32_t steps, int32_t batch,
+                                  float lr, float pos_weight, uint64_t seed, float* scratch, double* last_loss,
+                                  hipStream_t s) {
     float* grad = scratch;
     float* m = scratch + MLP_PARAMS;
     float* v = scratch + 2 * MLP_PARAMS;
@@ -1743,6 +1746,68 @@ louvain_status louvain_pruner_train(float* weights, const float* samples, int64_
     MLPCHK(hipStreamSynchronize(s));
     if (last_loss) *last_loss = hv;
     return LOUVAIN_OK;
+}
+
+// Scratch of louvain_pruner_train_noalloc: a file-scope device array, one
+// copy per GPU, kept until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+constexpr int64_t NOALLOC_SCRATCH_FLOATS = LOUVAIN_NOALLOC_SCRATCH_FLOATS;
+__device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+louvain_status noalloc_scratch(hipStream_t s, float** out) {
+    int dev = -1;
+    MLPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "device ordinal %d beyond the supported %d", dev, MAX_DEVICES);
+    if (s) {
+        hipDevice_t sd = -1;
+        MLPCHK(hipStreamGetDevice(s, &sd));
+        if ((int)sd != dev)
+            return fail(nullptr, LOUVAIN_ERR_INVALID, "stream belongs to device %d, current device is %d", (int)sd,
+                        dev);
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        MLPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (float*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LOUVAIN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+louvain_status louvain_pruner_train(float* weights, const float* samples, int64_t count, int32_t steps,
+                                    int32_t batch, float lr, float pos_weight, uint64_t seed, float* scratch,
+                                    double* last_loss, void* stream) {
+    if (!weights || !scratch || count <= 0 || !samples || steps < 0 || batch <= 0)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid arguments (need samples, count > 0, batch > 0)");
+    return train_with_scratch(weights, samples, count, steps, batch, lr, pos_weight, seed, scratch, last_loss,
+                              (hipStream_t)stream);
+}
+
+louvain_status louvain_pruner_train_noalloc(float* weights, const float* samples, int64_t count, int32_t steps,
+                                            int32_t batch, float lr, float pos_weight, uint64_t seed,
+                                            double* last_loss, void* stream) {
+    if (!weights || count <= 0 || !samples || steps < 0 || batch <= 0)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid arguments (need samples, count > 0, batch > 0)");
+    const int64_t need = louvain_pruner_scratch_floats(batch);
+    if (need > NOALLOC_SCRATCH_FLOATS)
+        return fail(nullptr, LOUVAIN_ERR_INVALID,
+                    "training needs %lld scratch floats, beyond the static maximum of %lld",
+                    (long long)need, (long long)NOALLOC_SCRATCH_FLOATS);
+    float* sp = nullptr;
+    const louvain_status st = noalloc_scratch((hipStream_t)stream, &sp);
+    if (st != LOUVAIN_OK) return st;
+    return train_with_scratch(weights, samples, count, steps, batch, lr, pos_weight, seed, sp, last_loss,
+                              (hipStream_t)stream);
 }
 
 const char* louvain_last_error(const louvain_t* h) {
