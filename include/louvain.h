@@ -283,12 +283,13 @@ louvain_status louvain_set_trace(louvain_t* h, louvain_iter_fn iter_fn, louvain_
  * graph (checked in create; LOUVAIN_ERR_INVALID otherwise).  Every graph goes
  * through the method of louvain_run on its own -- its own total weight W_k,
  * tolerance test, iteration count, shrink tests and pass count -- as if run
- * alone; the graphs share every kernel launch.  Pruners NONE and FLAGS in
- * both modes; LEARNED in ASYNC mode only (LOUVAIN_ERR_INVALID with SYNC): a
- * graph's pass then ends only at a full sweep whose exit test passes in that
- * graph, and sweeps are taken by all still-moving graphs together (after an
- * iteration in which any graph passed the tolerance test, or when the filter
- * keeps nothing).  Sample recording is refused on a batched handle.
+ * alone; the graphs share every kernel launch.  Every pruner in both modes;
+ * with LEARNED each graph follows its own sweep schedule, as in a lone run (a
+ * graph sweeps after one of its non-sweep iterations passes the tolerance
+ * test or when the filter keeps none of its vertices, and its pass ends only
+ * at one of its sweeps whose exit test passes in that graph), so SYNC results
+ * equal lone runs graph by graph.  Sample recording is refused on a batched
+ * handle.
  * louvain_get_membership writes, for each vertex, its community within its
  * graph (0 .. communities_k - 1, ascending final label); louvain_modularity is
  * refused on a batched handle.  louvain_workspace_size_batch: bytes for a

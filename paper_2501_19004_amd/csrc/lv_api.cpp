@@ -50,7 +50,7 @@ struct Layout {
     size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots, hpart;
     int64_t part_cap;
     // batched runs (count graphs; absent for a single graph)
-    size_t gid[2], gid0, Wg, gact, Sg, Pg, gcnt, cmin, vbase, gq, segcnt, segstart, prefall;
+    size_t gid[2], gid0, Wg, gact, Sg, Pg, gsweep, gany, gcnt, cmin, vbase, gq, segcnt, segstart, prefall;
     int64_t bitmap_words;
     int64_t pool_entries;
     size_t total;
@@ -113,6 +113,8 @@ bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
         L->gact = take(G);
         L->Sg = take(G * 16);
         L->Pg = take(G * 8);      // per graph: evaluations with a positive best gain
+        L->gsweep = take(G);      // per graph: the next iteration is its sweep (learned pruner)
+        L->gany = take(G);        // per graph: the learned filter kept a vertex
         L->gcnt = take(G * 16);   // per graph: vertices with arcs, used communities
         L->cmin = take(G * 4);
         L->vbase = take((G + 1) * 8);
@@ -409,8 +411,6 @@ louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t
             return fail(nullptr, LOUVAIN_ERR_INVALID, "vbase must start at 0 and end at n");
         for (int64_t k = 0; k < count; k++)
             if (vbase[k + 1] < vbase[k]) return fail(nullptr, LOUVAIN_ERR_INVALID, "vbase must be non-decreasing");
-        if (p->pruner == LOUVAIN_PRUNE_LEARNED && p->mode == LOUVAIN_SYNC)
-            return fail(nullptr, LOUVAIN_ERR_INVALID, "batched runs support the learned pruner in ASYNC mode only");
     }
     Layout lay;
     make_layout(g->n, g->nnz, count, p->async_slices, &lay);
@@ -637,7 +637,10 @@ louvain_status Runner::run() {
     u64* Sg_dev = batch ? at<u64>(Y.Sg) : nullptr;
     u64* Pg_dev = batch && learned ? at<u64>(Y.Pg) : nullptr;
     u64* gcnt_dev = batch ? at<u64>(Y.gcnt) : nullptr;
-    std::vector<uint8_t> alive(nbg, 1), act(nbg, 0), ran(nbg, 0), due(nbg, 1);
+    // gsw: graph g sweeps in the current iteration; want: in the next one
+    std::vector<uint8_t> alive(nbg, 1), act(nbg, 0), ran(nbg, 0), gsw(nbg, 1), want(nbg, 0), gany(nbg, 0);
+    uint8_t* gsweep_dev = batch && learned ? at<uint8_t>(Y.gsweep) : nullptr;
+    uint8_t* gany_dev = batch && learned ? at<uint8_t>(Y.gany) : nullptr;
     std::vector<int32_t> li_g(nbg, 0);
     std::vector<int64_t> nver(nbg, 0);
     std::vector<u64> hS(2 * nbg), hcnt(2 * nbg), hP(nbg);
@@ -651,17 +654,21 @@ louvain_status Runner::run() {
         for (u64 x : H->Wg) Wmax = std::max(Wmax, x);
         if (n0 > 0) HIPCHK(H, hipMemcpyAsync(gidb[0], at<int32_t>(Y.gid0), (size_t)n0 * 4, hipMemcpyDeviceToDevice, s));
     }
-    auto upload_act = [&]() -> louvain_status {
+    // per-graph byte arrays to the device (the staging buffer is reused by
+    // the next upload, so a pageable or shared one is waited for)
+    auto upload_bytes = [&](uint8_t* dev, const std::vector<uint8_t>& src) -> louvain_status {
         if (nbg <= (1 << 16)) {
-            memcpy(H->pinned_up, act.data(), (size_t)nbg);
-            HIPCHK(H, hipMemcpyAsync(gact_dev, H->pinned_up, (size_t)nbg, hipMemcpyHostToDevice, s));
-            if (!H->stage_owned) HIPCHK(H, hipStreamSynchronize(s));  // pageable source: reused next time
+            HIPCHK(H, hipStreamSynchronize(s));  // the previous upload has left the staging buffer
+            memcpy(H->pinned_up, src.data(), (size_t)nbg);
+            HIPCHK(H, hipMemcpyAsync(dev, H->pinned_up, (size_t)nbg, hipMemcpyHostToDevice, s));
+            if (!H->stage_owned) HIPCHK(H, hipStreamSynchronize(s));
         } else {
-            HIPCHK(H, hipMemcpyAsync(gact_dev, act.data(), (size_t)nbg, hipMemcpyHostToDevice, s));
+            HIPCHK(H, hipMemcpyAsync(dev, src.data(), (size_t)nbg, hipMemcpyHostToDevice, s));
             HIPCHK(H, hipStreamSynchronize(s));
         }
         return LOUVAIN_OK;
     };
+    auto upload_act = [&]() -> louvain_status { return upload_bytes(gact_dev, act); };
 
     for (int pass = 0; P.max_passes <= 0 || pass < P.max_passes; pass++) {
         const int64_t n = L.n;
@@ -671,7 +678,7 @@ louvain_status Runner::run() {
             for (int64_t g = 0; g < nbg; g++) {
                 act[g] = ran[g] = alive[g];
                 li_g[g] = P.max_iterations;
-                due[g] = 1;  // iteration 0 of a pass is every graph's sweep
+                gsw[g] = 1;  // iteration 0 of a pass is every graph's sweep
             }
             if ((st = upload_act()) != LOUVAIN_OK) return st;
             HIPCHK(H, hipMemsetAsync(gcnt_dev, 0, (size_t)nbg * 16, s));
@@ -738,10 +745,8 @@ louvain_status Runner::run() {
         // learned pruner (or sample recording): features and MLP over the
         // vertices flagged by iteration t, then the queue of iteration t + 1
         // from the kept flags (vertices of stopped graphs are left out)
-        auto filter_next = [&](int t, uint32_t stamp_next, uint8_t* fnext, int32_t* qnext, IterTotals* itp,
-                               int64_t* kept_out) -> louvain_status {
-            Ctl* hc = (Ctl*)H->pinned;
-            const int64_t before = H->smp_count;
+        auto run_filter = [&](int t, uint32_t stamp_next, uint8_t* fnext, const uint8_t* gsw_dev,
+                              uint8_t* gany_out) {
             FilterArgs fa{};
             fa.off = L.off;
             fa.n = n;
@@ -762,7 +767,16 @@ louvain_status Runner::run() {
             fa.cap = H->smp_buf ? H->smp_cap : 0;
             fa.per_mille = H->smp_buf ? H->smp_rate : 0;
             fa.ctl = ctl();
+            fa.gid = gid;
+            fa.gsweep = gsw_dev;
+            fa.gany = gany_out;
             timed(H, K_LEARN_FILTER, 0, [&] { launch_learn_filter(fa, L.t.off64, s); });
+        };
+        auto filter_next = [&](int t, uint32_t stamp_next, uint8_t* fnext, int32_t* qnext, IterTotals* itp,
+                               int64_t* kept_out, bool filter = true) -> louvain_status {
+            Ctl* hc = (Ctl*)H->pinned;
+            const int64_t before = H->smp_count;
+            if (filter) run_filter(t, stamp_next, fnext, nullptr, nullptr);
             if (prune)
                 timed(H, K_QUEUE, 0, [&] {
                     bucketize_vertices(n, vb, fnext, 1, gid, gact_dev, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
@@ -795,7 +809,12 @@ louvain_status Runner::run() {
             uint8_t* fnext = flags + (size_t)(stamp_next & 1) * (size_t)n0;
             const uint8_t* fcur = flags + (size_t)((stamp_next + 1) & 1) * (size_t)n0;
             if (prune) HIPCHK(H, hipMemsetAsync(fnext, 0, (size_t)n, s));
-            if (sweep) H->st.sweeps++;
+            if (sweep) {
+                H->st.sweeps++;
+            } else if (batch && learned) {
+                for (int64_t g = 0; g < nbg; g++)
+                    if (act[g] && gsw[g]) { H->st.sweeps++; break; }
+            }
             int32_t* qnext = qbuf[qsel];
             MoveArgs a{};
             a.off = L.off;
@@ -1010,58 +1029,71 @@ louvain_status Runner::run() {
             const bool may_end = sync || !pl;
             const bool conv = may_end && converged(S, W, P, pass);
             if (batch && learned) {
-                // LEARNED, batched: a graph's pass ends only at a sweep whose exit
-                // test passes in that graph (no evaluation with a positive best
-                // gain, or the tolerance test); sweeps are taken by all graphs
-                // together, after a non-sweep iteration where any graph passed
-                // the tolerance test or when the filter kept nothing.  The strict
-                // test is exact whoever asked for the sweep; the tolerance test
-                // ends a graph's pass only at a sweep that graph asked for itself
-                // (iteration 0, its own tolerance pass, or an empty filter), so
-                // its pass ends where it would end in a lone run's schedule.
-                bool changed = false, any = false, want_sweep = false;
+                // LEARNED, batched: every graph follows its own sweep schedule, as
+                // in a lone run.  A graph's pass ends only at one of its sweeps
+                // whose exit test passes in that graph (no evaluation with a
+                // positive best gain, or the tolerance test).  Its next iteration
+                // is a sweep after one of its non-sweep iterations passes the
+                // tolerance test, or when the filter keeps none of its vertices;
+                // in any other iteration its flagged vertices go through the
+                // filter.  A sweep evaluates every vertex of the graph.
+                bool changed = false, any = false, all_want = true;
                 for (int64_t g = 0; g < nbg; g++) {
                     if (!act[g]) continue;
                     const unsigned __int128 Sg = ((unsigned __int128)hS[2 * g + 1] << 64) + hS[2 * g];
                     const bool conv_g = may_end && converged(Sg, (int64_t)H->Wg[g], P, pass);
-                    const bool exit_g = P.guard_tolerance ? (due[g] && conv_g) : hP[g] == 0;
-                    if (sweep && exit_g) {
+                    if (gsw[g] && (P.guard_tolerance ? conv_g : hP[g] == 0)) {
                         li_g[g] = t + 1;
                         act[g] = 0;
+                        want[g] = 0;
                         changed = true;
                     } else {
                         any = true;
-                        due[g] = !sweep && conv_g;
-                        if (due[g]) want_sweep = true;
+                        want[g] = !gsw[g] && conv_g;
+                        all_want = all_want && want[g];
                     }
                 }
                 if (!any) { li = t + 1; break; }
                 if (changed && (st = upload_act()) != LOUVAIN_OK) return st;
-                bool next_sweep = want_sweep;
-                smp_lo = smp_hi = 0;
-                if (!next_sweep && t + 1 < P.max_iterations) {
-                    int64_t kept = 0;
-                    if ((st = filter_next(t, stamp_next, fnext, qnext, &it, &kept)) != LOUVAIN_OK) return st;
-                    if (kept == 0) {
-                        next_sweep = true;
-                        std::fill(due.begin(), due.end(), (uint8_t)1);  // every graph needs the certifying sweep
-                    } else {
-                        H->st.pruned += (int64_t)hc->pruned;
-                        csegs[0] = 0;
-                        for (int b = 0; b < NBT; b++) {
-                            counts[b] = it.qcount[b];
-                            csegs[b + 1] = csegs[b] + counts[b];
-                        }
-                        cur_list = qnext;
-                        qsel ^= 1;
+                if (t + 1 >= P.max_iterations) continue;  // the loop ends: no next queue
+                if (!all_want) {
+                    // filter with the sweeping graphs kept whole, then sweep the
+                    // graphs whose filtered queue came out empty
+                    if ((st = upload_bytes(gsweep_dev, want)) != LOUVAIN_OK) return st;
+                    HIPCHK(H, hipMemsetAsync(gany_dev, 0, (size_t)nbg, s));
+                    run_filter(t, stamp_next, fnext, gsweep_dev, gany_dev);
+                    if ((st = readback(H, gany.data(), gany_dev, (size_t)nbg)) != LOUVAIN_OK) return st;
+                    bool extra = false;
+                    all_want = true;
+                    for (int64_t g = 0; g < nbg; g++) {
+                        if (!act[g]) continue;
+                        if (!want[g] && !gany[g]) { want[g] = 1; extra = true; }
+                        all_want = all_want && want[g];
+                    }
+                    if (extra && !all_want) {
+                        if ((st = upload_bytes(gsweep_dev, want)) != LOUVAIN_OK) return st;
+                        run_filter(t, stamp_next, fnext, gsweep_dev, nullptr);
                     }
                 }
-                if (next_sweep) {
+                smp_lo = smp_hi = 0;
+                if (all_want) {
                     cur_list = blist;
                     for (int b = 0; b < NBT; b++) counts[b] = bcount[b];
                     for (int b = 0; b <= NBT; b++) csegs[b] = segs[b];
+                } else {
+                    int64_t kept = 0;
+                    if ((st = filter_next(t, stamp_next, fnext, qnext, &it, &kept, false)) != LOUVAIN_OK) return st;
+                    H->st.pruned += (int64_t)hc->pruned;
+                    csegs[0] = 0;
+                    for (int b = 0; b < NBT; b++) {
+                        counts[b] = it.qcount[b];
+                        csegs[b + 1] = csegs[b] + counts[b];
+                    }
+                    cur_list = qnext;
+                    qsel ^= 1;
                 }
-                sweep = next_sweep;
+                for (int64_t g = 0; g < nbg; g++) gsw[g] = act[g] ? want[g] : 0;
+                sweep = all_want;
                 continue;
             }
             if (batch) {

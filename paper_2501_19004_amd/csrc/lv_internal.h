@@ -129,6 +129,12 @@ struct FilterArgs {
     int64_t cap;
     int32_t per_mille;
     Ctl* ctl;
+    // batched runs: graph of every vertex; graphs whose next iteration is
+    // their own sweep (every vertex with an arc is kept, no MLP); set to 1 for
+    // every graph with at least one kept vertex (any of them may be NULL)
+    const int32_t* gid;
+    const uint8_t* gsweep;
+    uint8_t* gany;
 };
 
 // Lists of buckets 0..3 for one fused launch; blk_pre[b] is the first block

@@ -78,7 +78,9 @@ __device__ __forceinline__ void stage_weights(float* s_w, const float* w) {
 
 // Filter of the next iteration's flagged vertices (flags[v] set, or every
 // vertex with an arc when all = 1): features, MLP keep decision (a dropped
-// vertex is unflagged), sample recording.
+// vertex is unflagged), sample recording.  In a batch, the vertices of a
+// graph whose next iteration is its sweep are all kept (and flagged), and
+// every graph with a kept vertex is marked in gany.
 template <typename OffT>
 __global__ void __launch_bounds__(256) k_learn_filter(FilterArgs f) {
     __shared__ float s_w[MLP_PARAMS];
@@ -90,11 +92,15 @@ __global__ void __launch_bounds__(256) k_learn_filter(FilterArgs f) {
     bool dropped = false;
     if (v < f.n) {
         const OffT* off = (const OffT*)f.off;
-        bool flagged = f.all || f.flags[v];
+        const int32_t gv = f.gid ? f.gid[v] : -1;
+        const bool gsw = f.gsweep && gv >= 0 && f.gsweep[gv];
+        bool flagged = f.all || gsw || f.flags[v];
         const int64_t deg = flagged ? (int64_t)off[v + 1] - (int64_t)off[v] : 0;
         flagged = flagged && deg > 0;
-        const bool selected = flagged && f.per_mille > 0 && sample_selected(v, f.pass, f.t, f.per_mille);
-        if (flagged && (f.learned || selected)) {
+        if (gsw && flagged) f.flags[v] = 1;
+        const bool selected = flagged && !gsw && f.per_mille > 0 && sample_selected(v, f.pass, f.t, f.per_mille);
+        bool keep = flagged;
+        if (flagged && !gsw && (f.learned || selected)) {
             const i64 Kv = f.K[v];
             const int32_t m = f.nm[v];
             float x[MLP_IN];
@@ -106,7 +112,6 @@ __global__ void __launch_bounds__(256) k_learn_filter(FilterArgs f) {
             x[5] = (float)f.pass / 10.0f;
             x[6] = (float)f.t / 20.0f;
             x[7] = ratio(f.adv[v], Kv);
-            bool keep = true;
             if (f.learned) {
                 keep = mlp_logit(s_w, x) >= f.zt;
                 if (!keep) {
@@ -124,6 +129,7 @@ __global__ void __launch_bounds__(256) k_learn_filter(FilterArgs f) {
                 }
             }
         }
+        if (keep && f.gany && gv >= 0) f.gany[gv] = 1;
     }
     const u64 nd = __ballot(dropped);
     if ((threadIdx.x % WAVE) == 0 && nd) atomicAdd(&s_pruned, (u64)__popcll(nd));

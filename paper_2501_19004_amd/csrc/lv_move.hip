@@ -20,6 +20,7 @@
 // with plain byte stores, and the next queue is built by an ordered
 // compaction of the flagged vertices (lv_bucket.h).
 #include <algorithm>
+#include <type_traits>
 
 #include "lv_bucket.h"
 #include "lv_internal.h"
@@ -439,7 +440,7 @@ __device__ __forceinline__ int64_t queue_entry(const MoveArgs& a, int64_t slot) 
 
 // One block of a degree bucket: NG = BLOCK/G vertices, each evaluated by G
 // lanes with a CAP-slot table in LDS (keys/vals point at this block's LDS).
-template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE>
+template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE, bool WIDE>
 __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __restrict__ list, int32_t count,
                                            int64_t blk, int bucket, int32_t* s_keys, AccT* s_vals, uint16_t* s_list,
                                            MoveShm& sh) {
@@ -507,11 +508,13 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     group_sync<G>();
     const int32_t nocc = sh.ncl[grp];
 
-    Decision dcs = !a.wide
-        ? decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k64, sh.d, sh.v, sh.t, occ,
-                                     nocc)
-        : decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k128, sh.d, sh.v, sh.t,
-                                      occ, nocc);
+    Decision dcs;
+    if constexpr (!WIDE)
+        dcs = decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k64, sh.d, sh.v, sh.t,
+                                         occ, nocc);
+    else
+        dcs = decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k128, sh.d, sh.v, sh.t,
+                                          occ, nocc);
 
     if (a.learn && active && lane == 0) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
@@ -720,7 +723,9 @@ __device__ __forceinline__ void move_lanes(const MoveArgs& a, const int32_t* __r
     }
 }
 
-template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE>
+// WIDE: 128-bit gain arithmetic (W * max K >= 2^62); a separate instantiation
+// so that the common 64-bit kernels keep their register count.
+template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE, bool WIDE>
 __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, const int32_t* __restrict__ list,
                                                                 int32_t count) {
     constexpr int NG = (G > 256 ? G : 256) / G;
@@ -728,13 +733,14 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
     __shared__ AccT s_vals[NG * CAP];
     __shared__ uint16_t s_list[NG * CAP / 2];
     __shared__ MoveShm sh;
-    move_block<OffT, WK, AccT, G, CAP, MODE>(a, list, count, blockIdx.x, a.bucket, s_keys, s_vals, s_list, sh);
+    move_block<OffT, WK, AccT, G, CAP, MODE, WIDE>(a, list, count, blockIdx.x, a.bucket, s_keys, s_vals, s_list,
+                                                   sh);
 }
 
 // Buckets 0..3 (all 256-thread blocks) in one launch: block ranges
 // [blk_pre[b], blk_pre[b+1]) belong to bucket b; the tables live in dynamic
 // LDS sized for the largest of the four.
-template <typename OffT, int WK, typename AccT, int MODE>
+template <typename OffT, int WK, typename AccT, int MODE, bool WIDE>
 __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
     extern __shared__ __align__(16) char dyn[];
     __shared__ MoveShm sh;
@@ -749,14 +755,14 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
     switch (bk) {
         case 0: {
             static_assert(MOVE_G[0] == 1, "bucket 0 is the lane-per-vertex path");
-            if (!aa.wide) move_lanes<OffT, WK, MODE, i64>(aa, f.list[0], f.count[0], blk, 0, sh);
-            else move_lanes<OffT, WK, MODE, i128>(aa, f.list[0], f.count[0], blk, 0, sh);
+            using KeyT = typename std::conditional<WIDE, i128, i64>::type;
+            move_lanes<OffT, WK, MODE, KeyT>(aa, f.list[0], f.count[0], blk, 0, sh);
             break;
         }
         case 1: {
             constexpr int NG = 256 / MOVE_G[1];
             constexpr int TB = NG * MOVE_CAP[1];
-            move_block<OffT, WK, AccT, MOVE_G[1], MOVE_CAP[1], MODE>(
+            move_block<OffT, WK, AccT, MOVE_G[1], MOVE_CAP[1], MODE, WIDE>(
                 aa, f.list[1], f.count[1], blk, 1, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
                 (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
@@ -764,7 +770,7 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
         case 2: {
             constexpr int NG = 256 / MOVE_G[2];
             constexpr int TB = NG * MOVE_CAP[2];
-            move_block<OffT, WK, AccT, MOVE_G[2], MOVE_CAP[2], MODE>(
+            move_block<OffT, WK, AccT, MOVE_G[2], MOVE_CAP[2], MODE, WIDE>(
                 aa, f.list[2], f.count[2], blk, 2, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
                 (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
@@ -772,7 +778,7 @@ __global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
         default: {
             constexpr int NG = 256 / MOVE_G[3];
             constexpr int TB = NG * MOVE_CAP[3];
-            move_block<OffT, WK, AccT, MOVE_G[3], MOVE_CAP[3], MODE>(
+            move_block<OffT, WK, AccT, MOVE_G[3], MOVE_CAP[3], MODE, WIDE>(
                 aa, f.list[3], f.count[3], blk, 3, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
                 (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
@@ -1151,10 +1157,16 @@ void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, co
             constexpr int G = MOVE_G[b], CAP = MOVE_CAP[b];
             constexpr int BLOCK = G > 256 ? G : 256;
             const unsigned grid = blocks_for(count, BLOCK / G);
-            if (mode == M_SYNC) k_move_lds<OffT, WK, AccT, G, CAP, M_SYNC><<<grid, BLOCK, 0, s>>>(a, list, count);
-            else if (mode == M_ASYNC_CACHED)
-                k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_CACHED><<<grid, BLOCK, 0, s>>>(a, list, count);
-            else k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_COHERENT><<<grid, BLOCK, 0, s>>>(a, list, count);
+            auto run = [&](auto wtag) {
+                constexpr bool WIDE = decltype(wtag)::value != 0;
+                if (mode == M_SYNC)
+                    k_move_lds<OffT, WK, AccT, G, CAP, M_SYNC, WIDE><<<grid, BLOCK, 0, s>>>(a, list, count);
+                else if (mode == M_ASYNC_CACHED)
+                    k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_CACHED, WIDE><<<grid, BLOCK, 0, s>>>(a, list, count);
+                else k_move_lds<OffT, WK, AccT, G, CAP, M_ASYNC_COHERENT, WIDE><<<grid, BLOCK, 0, s>>>(a, list, count);
+            };
+            if (a.wide) run(IntTag<1>{});
+            else run(IntTag<0>{});
         };
         // buckets 0-3 run in k_move_fused; only the workgroup bucket has its own launch
         if (bucket == 4) go(IntTag<4>{});
@@ -1217,9 +1229,15 @@ void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const Fu
         size_t shm = 0;
         for (int b = 1; b < 4; b++)  // bucket 0 (one vertex per lane) has no table
             shm = std::max(shm, (size_t)(256 / MOVE_G[b]) * MOVE_CAP[b] * (4 + sizeof(AccT) + 1));
-        if (mode == M_SYNC) k_move_fused<OffT, WK, AccT, M_SYNC><<<(unsigned)grid, 256, shm, s>>>(a, f);
-        else if (mode == M_ASYNC_CACHED) k_move_fused<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)grid, 256, shm, s>>>(a, f);
-        else k_move_fused<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)grid, 256, shm, s>>>(a, f);
+        auto run = [&](auto wtag) {
+            constexpr bool WIDE = decltype(wtag)::value != 0;
+            if (mode == M_SYNC) k_move_fused<OffT, WK, AccT, M_SYNC, WIDE><<<(unsigned)grid, 256, shm, s>>>(a, f);
+            else if (mode == M_ASYNC_CACHED)
+                k_move_fused<OffT, WK, AccT, M_ASYNC_CACHED, WIDE><<<(unsigned)grid, 256, shm, s>>>(a, f);
+            else k_move_fused<OffT, WK, AccT, M_ASYNC_COHERENT, WIDE><<<(unsigned)grid, 256, shm, s>>>(a, f);
+        };
+        if (a.wide) run(IntTag<1>{});
+        else run(IntTag<0>{});
     });
 }
 

@@ -162,10 +162,9 @@ def test_batch_create_rejects_bad_arguments(lib):
     learned = lv.louvain_params_default()
     learned.pruner = lv.PRUNE_LEARNED
     learned.pruner_weights = fake
-    learned.mode = lv.SYNC
-    assert create([0, 5, 10], 2, learned) == lv.LOUVAIN_ERR_INVALID   # learned + batched: ASYNC only
-    learned.mode = lv.ASYNC
-    assert create([0, 5, 10], 2, learned) == lv.LOUVAIN_ERR_WORKSPACE  # accepted; no workspace
+    for mode in (lv.SYNC, lv.ASYNC):
+        learned.mode = mode
+        assert create([0, 5, 10], 2, learned) == lv.LOUVAIN_ERR_WORKSPACE  # accepted; no workspace
     assert create([0, 5, 10], 2) == lv.LOUVAIN_ERR_WORKSPACE    # arguments fine, no workspace
     single = lv.louvain_workspace_size(g, p)
     assert lv.louvain_workspace_size_batch(g, 2, p) > single == lv.louvain_workspace_size_batch(g, 0, p)

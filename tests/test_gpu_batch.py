@@ -1,9 +1,10 @@
 """GPU parity of batched runs: many independent graphs in one run.
 
 Every graph of a batch must come out exactly as the oracle's run of that
-graph alone: in SYNC mode the same membership, passes, iterations and
-community count, and the exact modularity of the GPU membership equals the
-oracle's evaluation of it with the graph's own total weight.  ASYNC runs
+graph alone: in SYNC mode (flag or learned pruning) the same membership,
+passes, iterations and community count, and the exact modularity of the GPU
+membership equals the oracle's evaluation of it with the graph's own total
+weight.  ASYNC runs
 must reach, graph by graph, modularity within 0.002 of the oracle's, where
 the oracle's modularity is the lowest it reaches over the identity vertex
 order and seeded relabellings (tests/orders.py: the method leaves the
@@ -178,6 +179,26 @@ def test_batch_async_learned_quality(theta, guard):
     print(f"Q_gpu - (floor over orders) per graph: min {min(d):+.5f} mean {np.mean(d):+.5f}")
     bad = [(k, graphs[k].name, round(d[k], 5)) for k in range(len(graphs)) if d[k] < 0]
     assert not bad, bad
+
+
+@pytest.mark.parametrize("theta,guard", [(0.5, 1), (0.55, 0), (0.45, 1), (0.0, 0), (1.0, 1)])
+def test_batch_sync_learned_equals_lone_oracle_runs(theta, guard):
+    """SYNC batches with the learned pruner: every graph follows its own sweep
+    schedule, so each graph's membership, passes, iterations, communities and
+    exact modularity equal the oracle's lone SYNC run with the same weights,
+    threshold and exit test."""
+    graphs = mixed_batch() + sbm_batch(16, 7)
+    w = rand_weights(3)
+    parts, q, num, den, passes, iters, comms = run_batch(graphs, lv.SYNC, pruner=lv.PRUNE_LEARNED, pruner_weights=w,
+                                                         pruner_threshold=theta, guard_tolerance=guard)
+    P = oracle.Params(mode=oracle.SYNC, prune=oracle.PRUNE_LEARNED, mlp=w.cpu().numpy(), threshold=theta,
+                      guard_tolerance=guard)
+    for k, g in enumerate(graphs):
+        ref = oracle.louvain(g, P)
+        where = (k, g.name)
+        assert np.array_equal(parts[k], ref.membership), where
+        assert (passes[k], iters[k], comms[k]) == (ref.passes, ref.iterations, ref.communities), where
+        assert (num[k], den[k]) == oracle.modularity_parts(g, parts[k]), where
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.5, 1.0])
