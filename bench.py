@@ -213,6 +213,92 @@ def learned_leg(lv, torch, nnz, graph, mode, args, q_plain, dt_plain, wts, info)
     return legs
 
 
+def ablation_leg(lv, torch, graph, nnz, mode, reps):
+    """The paper's GPU design-space experiments (Section 4.3) repeated on this
+    workload: Pick-Less period (community swaps), the degree that switches a
+    vertex from workgroup LDS tables to global hub tables (the paper's switch
+    degree between its two kernels), the low-degree bucket boundaries, and the
+    width of the hash-table values (32-bit when sums fit, or always 64-bit).
+    Each setting: 1 warm-up, then the median of `reps` runs and its Q."""
+    off, idx, w = graph
+    out = {}
+
+    def one(**kw):
+        L = lv.Louvain(off, idx, w, mode=mode, **kw)
+        dt, q, st = timed_runs(L, reps, 1)
+        L.close()
+        del L
+        torch.cuda.empty_cache()
+        return {"ms_per_step": round(dt * 1e3, 3), "value": round(nnz / dt / 1e6, 2), "modularity": round(q, 6),
+                "passes": st.passes, "iterations": st.iterations}
+    out["pick_less_period"] = {str(r): one(pick_less=r) for r in (0, 2, 4, 8, 16)}
+    out["hub_switch_degree"] = {str(d): one(bucket_max_degree=[0, 0, 0, 0, d]) for d in (512, 1024, 2048, 4096)}
+    out["low_degree_buckets"] = {",".join(map(str, b)): one(bucket_max_degree=b + [0])
+                                 for b in ([8, 32, 128, 512], [4, 16, 64, 256], [8, 16, 64, 512], [2, 32, 128, 512])}
+    out["table_values"] = {name: one(table_values_64=v) for name, v in (("auto", 0), ("int64", 1))}
+    for k, v in out.items():
+        log(f"ablation {k}: " + ", ".join(f"{s}: {r['ms_per_step']} ms Q={r['modularity']}" for s, r in v.items()))
+    return out
+
+
+def handoff_leg(lv, torch, graph, nnz, mode, dt_full, passes, reps):
+    """Late-pass handoff study: after pass p, either the GPU continues (its
+    time for the remaining passes = full run - run stopped after p passes),
+    or the super-graph of pass p goes to the host, where the OpenMP CPU
+    baseline runs the remaining passes on all host cores (with the tolerance
+    the run would have reached, 0.01 / 10^p) after a device-to-host copy."""
+    import numpy as np
+
+    import cpu_baseline
+    import graphgen as gg
+    off, idx, w = graph
+    threads = max(1, min(16, host_info().get("affinity_cores") or os.cpu_count() or 1, cpu_baseline.max_threads()))
+    out = {"threads": threads, "full_run_ms": round(dt_full * 1e3, 3), "points": []}
+    for p in range(1, passes):
+        L = lv.Louvain(off, idx, w, mode=mode, max_passes=p)
+        dtp, _, _ = timed_runs(L, reps, 1)
+        L.close()
+        del L
+        sup = {}
+
+        def on_pass(pp, n, o, i, ww, it, p=p):
+            if pp == p - 1:
+                sup["g"] = gg.CSRGraph(int(n), o, i, ww, f"super-graph after pass {p}")
+        L = lv.Louvain(off, idx, w, mode=mode, max_passes=p + 1)
+        L.trace(None, on_pass)
+        L.run()
+        L.close()
+        del L
+        torch.cuda.empty_cache()
+        gp = sup.get("g")
+        if gp is None:
+            break
+        nbytes = gp.offsets.nbytes + gp.indices.nbytes + gp.weights.nbytes
+        dev = torch.empty(max(nbytes // 4, 1), dtype=torch.int32, device="cuda:0")
+        host = torch.empty(dev.shape, dtype=torch.int32, pin_memory=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host.copy_(dev)
+        torch.cuda.synchronize()
+        t_copy = time.perf_counter() - t0
+        del dev, host
+        cpu_baseline.louvain(gp, threads=threads, max_passes=10 - p, tol_den=100 * 10 ** p)  # warm-up
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            cpu_baseline.louvain(gp, threads=threads, max_passes=10 - p, tol_den=100 * 10 ** p)
+            ts.append(time.perf_counter() - t0)
+        t_cpu = float(np.median(ts))
+        point = {"after_pass": p, "super_vertices": gp.n, "super_arcs": int(gp.offsets[-1]),
+                 "gpu_rest_ms": round((dt_full - dtp) * 1e3, 3), "copy_ms": round(t_copy * 1e3, 3),
+                 "cpu_rest_ms": round(t_cpu * 1e3, 3),
+                 "handoff_faster": bool(t_copy + t_cpu < dt_full - dtp)}
+        out["points"].append(point)
+        log(f"handoff after pass {p}: {gp.n} vertices, {point['super_arcs']} arcs; GPU rest {point['gpu_rest_ms']} ms, "
+            f"copy + CPU {point['copy_ms']} + {point['cpu_rest_ms']} ms")
+    return out
+
+
 def batch_graphs(count, nmax, threads):
     """SBM graphs of graphgen.sbm_batch_specs (equal-size communities, 4 to
     64 of them, average degree uniform in [8, 32], intra/inter degree ratio
@@ -364,6 +450,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-pruner leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-SBM leg")
     ap.add_argument("--no-autotune", action="store_true", help="skip the degree-bucket autotuner leg")
+    ap.add_argument("--handoff", action="store_true",
+                    help="also run the late-pass handoff study (GPU vs OpenMP host after each pass)")
+    ap.add_argument("--ablations", action="store_true",
+                    help="also run the design-space experiments (Pick-Less period, switch degrees, value width)")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-nmax", type=int, default=200000)
     ap.add_argument("--batch-check", type=int, default=64, help="batch graphs checked against the oracle")
@@ -447,6 +537,8 @@ def main():
     L.close()
     del L
     torch.cuda.empty_cache()
+    ablations = ablation_leg(lv, torch, (off, idx, w), nnz, mode, args.aux_steps) if args.ablations else None
+    handoff = handoff_leg(lv, torch, (off, idx, w), nnz, mode, dt, st.passes, args.aux_steps) if args.handoff else None
     learned = wts = None
     if not args.no_learned:
         wts, info = train_pruner(lv, torch, mode)
@@ -490,6 +582,10 @@ def main():
         "autotuned": tuned,
         "batch": batch,
     }
+    if ablations is not None:
+        out["ablations"] = ablations
+    if handoff is not None:
+        out["handoff"] = handoff
     print(json.dumps(out))
 
 

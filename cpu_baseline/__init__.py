@@ -58,15 +58,17 @@ def max_threads() -> int:
     return int(_load().gve_max_threads())
 
 
-def louvain(g, threads: int = 0, max_iterations: int = 20, max_passes: int = 10):
+def louvain(g, threads: int = 0, max_iterations: int = 20, max_passes: int = 10, tol_den: int = 100):
     """Run on a graphgen.CSRGraph; returns (membership int32[n], stats dict).
-    Paper defaults: tau 0.01 dropped 10x per pass, tau_agg 0.8."""
+    Paper defaults: tau = 1/tol_den = 0.01 dropped 10x per pass, tau_agg 0.8
+    (a run that continues another one after p passes starts at
+    tol_den = 100 * 10^p)."""
     lib = _load()
     off = np.ascontiguousarray(g.offsets, dtype=np.int64)
     idx = np.ascontiguousarray(g.indices, dtype=np.int32)
     w = np.ascontiguousarray(g.weights, dtype=np.int64)
     memb = np.empty(max(g.n, 1), dtype=np.int32)
-    p = _Params(max_iterations, max_passes, 1, 100, 10, 4, 5)
+    p = _Params(max_iterations, max_passes, 1, tol_den, 10, 4, 5)
     st = _Stats()
     rc = lib.gve_louvain(g.n, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                          idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),

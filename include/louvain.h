@@ -162,7 +162,12 @@ typedef struct {
      * the id range; in a batch, every graph); 0 = slice s takes the s-th
      * contiguous share (default; closer to the sequential order). */
     int32_t async_interleave;
-    int32_t reserved2;
+    /* Width of the hash-table values (the accumulated K_{i->d} of local
+     * moving and the merged weights of aggregation): 0 (default) = 32-bit
+     * whenever the sums cannot reach 2^32, else 64-bit; 1 = always 64-bit.
+     * Results do not depend on it (the paper's "datatype for hashtable
+     * values" experiment, Section 4.3, made exact). */
+    int32_t table_values_64;
 } louvain_params;
 
 /* Per-run counters, filled by louvain_get_stats after louvain_run. */

@@ -55,7 +55,7 @@ class LouvainParams(ctypes.Structure):
                 ("guard_tolerance", ctypes.c_int32), ("async_slice_min", ctypes.c_int32),
                 ("async_hub_groups", ctypes.c_int32), ("async_min_label", ctypes.c_int32),
                 ("pruner_weights", ctypes.c_void_p), ("pruner_threshold", ctypes.c_double),
-                ("async_interleave", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("async_interleave", ctypes.c_int32), ("table_values_64", ctypes.c_int32)]
 
 
 class LouvainStats(ctypes.Structure):
@@ -470,7 +470,7 @@ class Louvain:
                 ww = np.ctypeslib.as_array(w, shape=(m,)).copy() if m else np.zeros(0, np.int64)
                 on_pass(int(p), int(n), o, ii, ww, int(iters))
 
-        self._cb = (ITER_FN(it), PASS_FN(pa))
+        self._cb = (ITER_FN(it) if on_iter else ITER_FN(), PASS_FN(pa) if on_pass else PASS_FN())
         louvain_set_trace(self.h, self._cb[0], self._cb[1])
 
     def collect_samples(self, capacity: int, sample_per_mille: int):

@@ -354,6 +354,7 @@ void louvain_params_default(louvain_params* p) {
     p->async_hub_groups = 32;
     p->async_min_label = 1;
     p->async_interleave = 0;
+    p->table_values_64 = 0;
     p->pruner_weights = nullptr;
     p->pruner_threshold = 0.5;
 }
@@ -398,7 +399,8 @@ louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t
         p->agg_num < 0 || p->pick_less < 0 || (p->mode != LOUVAIN_ASYNC && p->mode != LOUVAIN_SYNC) ||
         (p->pruner != LOUVAIN_PRUNE_NONE && p->pruner != LOUVAIN_PRUNE_FLAGS &&
          p->pruner != LOUVAIN_PRUNE_LEARNED) ||
-        (p->guard_tolerance != 0 && p->guard_tolerance != 1) || p->async_slices < 0 || p->async_slice_min < 0 ||
+        (p->guard_tolerance != 0 && p->guard_tolerance != 1) ||
+        (p->table_values_64 != 0 && p->table_values_64 != 1) || p->async_slices < 0 || p->async_slice_min < 0 ||
         p->async_hub_groups < 0)
         return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid parameter value");
     if (p->pruner == LOUVAIN_PRUNE_LEARNED && !p->pruner_weights)
@@ -728,7 +730,7 @@ louvain_status Runner::run() {
         if ((st = readback(H, &kmax, &ctl()->kmax, sizeof(u64))) != LOUVAIN_OK) return st;
         const bool wide = (unsigned __int128)Wmax * kmax >= ((unsigned __int128)1 << 62);
         LevelView LM = L;
-        LM.t.acc64 = kmax >= ((u64)1 << 32);
+        LM.t.acc64 = P.table_values_64 || kmax >= ((u64)1 << 32);
 
         // ---------------- local moving
         int32_t li = P.max_iterations;
@@ -1274,7 +1276,7 @@ louvain_status Runner::run() {
         A.rowlen = at<int32_t>(Y.rowlen);
         A.out_w64 = H->sup_wk == 2;
         LevelView LA = L;
-        LA.t.acc64 = (u64)W >= ((u64)1 << 32);
+        LA.t.acc64 = P.table_values_64 || (u64)W >= ((u64)1 << 32);
         for (int b = 0; b < NB_AGG; b++) {
             if (acount[b] <= 0) continue;
             timed(H, K_AGG0 + b, 0, [&] { launch_aggregate(LA, b, A, alist + asegs[b], acount[b], s); });

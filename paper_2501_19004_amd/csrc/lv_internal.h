@@ -14,7 +14,7 @@ namespace lv {
 // lane with its row in registers (no table; CAP / 2 = 8 is its largest
 // degree).  Bucket NB_MOVE is the global-memory ("hub") path.
 constexpr int NB_MOVE = 5;
-constexpr int MOVE_G[NB_MOVE] = {1, 16, 64, 256, 1024};
+constexpr int MOVE_G[NB_MOVE] = {1, 8, 32, 256, 1024};
 constexpr int MOVE_CAP[NB_MOVE] = {16, 64, 256, 1024, 8192};
 constexpr int MOVE_DEFAULT_MAX[NB_MOVE] = {8, 32, 128, 512, 4096};
 constexpr int HUB_CH = 4096;    // arcs per hub insert chunk (one workgroup)

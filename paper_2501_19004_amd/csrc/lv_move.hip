@@ -740,8 +740,11 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
 // Buckets 0..3 (all 256-thread blocks) in one launch: block ranges
 // [blk_pre[b], blk_pre[b+1]) belong to bucket b; the tables live in dynamic
 // LDS sized for the largest of the four.
+// Six waves per SIMD fit the 64-bit variants without spilling (the default
+// allocation leaves five); the 128-bit variants keep the compiler's choice.
 template <typename OffT, int WK, typename AccT, int MODE, bool WIDE>
-__global__ void __launch_bounds__(256) k_move_fused(MoveArgs a, FusedLists f) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 6, 8)))
+k_move_fused(MoveArgs a, FusedLists f) {
     extern __shared__ __align__(16) char dyn[];
     __shared__ MoveShm sh;
     const int64_t b = (int64_t)blockIdx.x;

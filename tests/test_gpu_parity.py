@@ -22,7 +22,8 @@ lv = pytest.importorskip("paper_2501_19004_amd")
 ALL_HUB = dict(bucket_max_degree=[-1] * 5, agg_bucket_max=[-1] * 4)
 ONLY_WG = dict(bucket_max_degree=[-1, -1, -1, -1, 4096], agg_bucket_max=[-1, -1, -1, 4096])
 SMALL_B = dict(bucket_max_degree=[2, 8, 16, 64, 128], agg_bucket_max=[4, 16, 64, 256])
-CONFIGS = {"default": {}, "all_hub": ALL_HUB, "only_wg": ONLY_WG, "small_buckets": SMALL_B}
+CONFIGS = {"default": {}, "all_hub": ALL_HUB, "only_wg": ONLY_WG, "small_buckets": SMALL_B,
+           "values64": dict(table_values_64=1)}
 
 
 def star_plus_cliques(leaves=9000, cliques=30, k=6):
