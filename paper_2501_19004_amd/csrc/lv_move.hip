@@ -939,18 +939,32 @@ __device__ __forceinline__ void hub_decide_block(const MoveArgs& a, int32_t h, i
     AccT* vals = (AccT*)a.hub_vals + toff;
     const int32_t* slots = a.hub_slots + toff / 2;
     const int64_t nocc = a.hub_cnt[h];
-    const int64_t lo = nocc * k / nch, hi = nocc * (k + 1) / nch;
     const int32_t c = ld_c<MODE>(&a.Cp[v]);
     const i64 Ki = a.K[v];
     const int32_t gv = a.gid ? a.gid[v] : -1;
     const i64 Wv = gv >= 0 ? (i64)a.Wg[gv] : a.W;
-    const Best<KeyT> b = scan_table<G, MODE, KeyT, AccT>(a, Wv, keys, vals, cap, tid, c, Ki, s_k, s_d, s_v, s_t,
-                                                         slots + lo, hi - lo);
-    // clear this block's share of the table for the next iteration
-    for (int64_t x = lo + tid; x < hi; x += G) {
-        const int32_t sl = slots[x];
-        keys[sl] = EMPTY_KEY;
-        vals[sl] = 0;
+    Best<KeyT> b;
+    if (nocc * 8 >= cap) {
+        // a well-filled table (at least 1/8 occupied, as after the first
+        // iteration of a pass): scan this block's share of the slots in order,
+        // with coalesced loads, and clear it with coalesced stores
+        const int64_t t0 = cap * k / nch, t1 = cap * (k + 1) / nch;
+        b = scan_table<G, MODE, KeyT, AccT>(a, Wv, keys + t0, vals + t0, t1 - t0, tid, c, Ki, s_k, s_d, s_v, s_t,
+                                            (const int32_t*)nullptr, 0);
+        for (int64_t x = t0 + tid; x < t1; x += G) {
+            keys[x] = EMPTY_KEY;
+            vals[x] = 0;
+        }
+    } else {
+        // a sparse table: only the listed occupied slots
+        const int64_t lo = nocc * k / nch, hi = nocc * (k + 1) / nch;
+        b = scan_table<G, MODE, KeyT, AccT>(a, Wv, keys, vals, cap, tid, c, Ki, s_k, s_d, s_v, s_t, slots + lo,
+                                            hi - lo);
+        for (int64_t x = lo + tid; x < hi; x += G) {
+            const int32_t sl = slots[x];
+            keys[sl] = EMPTY_KEY;
+            vals[sl] = 0;
+        }
     }
     if (nch == 1) {
         hub_finish<MODE, KeyT>(a, h, v, (i64)off[v + 1] - (i64)off[v], b, tid);
