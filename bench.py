@@ -356,19 +356,24 @@ def batch_leg(lv, torch, args, wts=None):
             out[name]["speedup_vs_async"] = round(out["async"]["ms_per_step"] / out[name]["ms_per_step"], 3)
             out[name]["dq_mean_vs_async"] = round(float(q.mean()) - out["async"]["mean_modularity"], 6)
         if not args.no_cpu_baseline and mode == lv.ASYNC and nchk:
-            # per-graph quality against the sequential oracle (identity order)
+            # per-graph quality against the sequential oracle: its identity
+            # order, and the lowest Q it reaches over that order and 8 seeded
+            # relabellings (the yardstick of the GPU tests: the method leaves
+            # the visiting order open)
             if qo is None:
-                import oracle
+                from oracle.orders import oracle_q_orders
 
                 def oq(gk):
-                    gk.weights = gk.weights.astype(np.int64)
-                    return oracle.modularity(gk, oracle.louvain(gk).membership)
+                    return oracle_q_orders(gk)
                 with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-                    qo = list(ex.map(oq, graphs[:nchk]))
-            d = q[:nchk] - np.array(qo)
-            out[name]["dq_vs_oracle_first_graphs"] = {"graphs": nchk, "mean": round(float(d.mean()), 6),
-                                                      "min": round(float(d.min()), 6),
-                                                      "below_minus_0.002": int((d < -0.002).sum())}
+                    qo = np.array(list(ex.map(oq, graphs[:nchk])))
+            d_id = q[:nchk] - qo[:, 0]
+            d_fl = q[:nchk] - qo.min(axis=1)
+            out[name]["dq_vs_oracle_first_graphs"] = {
+                "graphs": nchk, "identity_order": {"mean": round(float(d_id.mean()), 6),
+                                                   "min": round(float(d_id.min()), 6)},
+                "lowest_over_9_orders": {"mean": round(float(d_fl.mean()), 6), "min": round(float(d_fl.min()), 6),
+                                         "below_minus_0.002": int((d_fl < -0.002).sum())}}
         log(f"batch {name}: {dt * 1e3:.2f} ms/run, {na / dt / 1e6:.1f} M arcs/s, mean Q {q.mean():.4f}")
     del off, idx, w
     return out
@@ -533,8 +538,10 @@ def main():
     plain_params = (L.params.async_coherent, L.params.async_min_label, L.params.async_slices)
     tuned = None
     if not args.no_autotune:
-        cands = ([[8, 32, 128, 1024, 4096], [8, 32, 128, 512, 8192]] if args.workload == "rmat27" else
-                 [[8, 32, 128, 1024, 4096], [8, 16, 64, 256, 4096], [4, 16, 64, 512, 4096], [16, 32, 128, 512, 4096]])
+        # every candidate lowers at least one threshold below the library's (8, 32, 128, 512, 4096):
+        # thresholds above a bucket's table capacity are clamped to it and would repeat the defaults
+        cands = ([[8, 16, 128, 512, 4096], [8, 32, 128, 256, 4096]] if args.workload == "rmat27" else
+                 [[8, 16, 128, 512, 4096], [8, 32, 128, 256, 4096], [4, 32, 128, 512, 4096], [8, 32, 64, 512, 4096]])
         reps = 2 if args.workload == "rmat27" else 3
         t1 = time.time()
         best, cms = L.autotune(cands, reps=reps)

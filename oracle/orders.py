@@ -1,4 +1,6 @@
-"""Visiting-order spread of the sequential oracle (test helper).
+"""Visiting-order spread of the sequential oracle (test infrastructure, like
+the rest of this package: used by the tests and by the benchmark's quality
+report, never by the GPU library).
 
 The paper leaves the order in which the asynchronous local-moving phase
 visits vertices open: the multicore and GPU designs process vertices
@@ -17,7 +19,8 @@ from __future__ import annotations
 import numpy as np
 
 import graphgen as gg
-import oracle
+
+from . import louvain, modularity
 
 ORDERS = 8      # seeded relabellings besides the identity order
 ORDER_SEED = 100
@@ -42,10 +45,10 @@ def oracle_q_orders(g, orders: int = ORDERS, seed: int = ORDER_SEED, params=None
     in `orders` seeded relabellings (each evaluated on its own graph; Q is
     invariant under relabelling)."""
     g = gg.CSRGraph(g.n, g.offsets, g.indices, np.asarray(g.weights, dtype=np.int64), g.name)
-    qs = [oracle.modularity(g, oracle.louvain(g, params).membership)]
+    qs = [modularity(g, louvain(g, params).membership)]
     for r in range(orders):
         gp = relabel(g, np.random.default_rng(seed + r).permutation(g.n))
-        qs.append(oracle.modularity(gp, oracle.louvain(gp, params).membership))
+        qs.append(modularity(gp, louvain(gp, params).membership))
     return qs
 
 

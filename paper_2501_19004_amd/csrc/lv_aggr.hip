@@ -193,11 +193,15 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_aggregate_lds(Graph<OffT,
 #pragma unroll
     for (int q = 0; q < PER; q++)
         if (rk[q] != EMPTY_KEY) { keys[at] = rk[q]; vals[at] = rv[q]; at++; }
-    int64_t P = 1;
-    while (P < L) P <<= 1;
-    for (i64 x = L + lane; x < P; x += G) { keys[x] = EMPTY_KEY; vals[x] = 0; }
-    group_sync<G>();
-    bitonic_sort_group<G, AccT>(keys, vals, P, lane);
+    if (a.sorted) {
+        int64_t P = 1;
+        while (P < L) P <<= 1;
+        for (i64 x = L + lane; x < P; x += G) { keys[x] = EMPTY_KEY; vals[x] = 0; }
+        group_sync<G>();
+        bitonic_sort_group<G, AccT>(keys, vals, P, lane);
+    } else {
+        group_sync<G>();
+    }
     if (active) {
         const i64 h = a.hoff[c];
         for (i64 x = lane; x < L; x += G) {
@@ -421,6 +425,17 @@ __global__ void __launch_bounds__(1024) k_big_extract(BigArgs a) {
         const int32_t* slots = a.slots + toff / 2;
         const int64_t L = a.cnt[h];
         const int64_t base = a.hoff[c];
+        if (!a.sorted) {
+            // table order: the listed occupied slots as they are
+            for (int64_t x = tid; x < L; x += G) {
+                const int32_t sl = slots[x];
+                a.hidx[base + x] = keys[sl];
+                if (a.out_w64) ((i64*)a.hw)[base + x] = (i64)vals[sl];
+                else ((int32_t*)a.hw)[base + x] = (int32_t)vals[sl];
+            }
+            if (tid == 0) a.rowlen[c] = (int32_t)L;
+            continue;
+        }
         if (L <= BIG_SORT_MAX) {
             // the listed entries, padded to a power of two, sorted in LDS
             int64_t P = 1;

@@ -1275,6 +1275,10 @@ louvain_status Runner::run() {
         A.hw = at<void>(Y.hw);
         A.rowlen = at<int32_t>(Y.rowlen);
         A.out_w64 = H->sup_wk == 2;
+        // Rows are sorted by neighbour id only when a pass callback receives
+        // the super-graphs (the canonical form the traces compare); no
+        // decision of the method depends on the order of a row's entries.
+        A.sorted = H->pafn != nullptr;
         LevelView LA = L;
         LA.t.acc64 = P.table_values_64 || (u64)W >= ((u64)1 << 32);
         for (int b = 0; b < NB_AGG; b++) {
@@ -1326,6 +1330,7 @@ louvain_status Runner::run() {
                 B.words = (ncom + 31) / 32;
                 B.cnt = at<int32_t>(Y.hcnt) + gr.first;
                 B.slots = at<int32_t>(Y.hslots);
+                B.sorted = A.sorted;
                 const int64_t nchunks = chpre[gr.second] - chpre[gr.first];
                 HIPCHK(H, hipMemsetAsync(B.cnt, 0, (size_t)B.nbig * 4, s));
                 timed(H, K_AGG_BIG_INSERT, 0, [&] {

@@ -221,6 +221,7 @@ struct AggArgs {
     void* hw;                // holey weights (int32 or int64, per out_w64)
     int32_t* rowlen;         // distinct count per community
     int32_t out_w64;         // super-graph weights int64
+    int32_t sorted;          // 1: rows ascending by neighbour id; 0: in table order
 };
 void launch_mark_used(const int32_t* Cp, int64_t n, int32_t* used, hipStream_t s);
 void launch_relabel(int32_t* Cp, int64_t n, const int32_t* newid, hipStream_t s);
@@ -264,6 +265,7 @@ struct BigArgs {
     int64_t words;             // ceil(ncom / 32)
     int32_t* cnt;              // per big community of the group: occupied table slots (zeroed by the host)
     int32_t* slots;            // occupied slot lists, community h's at its table offset / 2
+    int32_t sorted;            // 1: rows ascending by neighbour id; 0: in table order
 };
 constexpr int BIG_SORT_MAX = 8192;  // rows up to this length are sorted in LDS at extraction
 void launch_member_deg(const LevelView& L, const int32_t* members, int64_t n, int64_t* md, hipStream_t s);

@@ -13,7 +13,7 @@ import pytest
 import cpu_baseline
 import graphgen as gg
 import oracle
-from orders import async_floor
+from oracle.orders import async_floor
 
 
 def q_of(g, memb):

@@ -7,7 +7,7 @@ membership equals the oracle's evaluation of it with the graph's own total
 weight.  ASYNC runs
 must reach, graph by graph, modularity within 0.002 of the oracle's, where
 the oracle's modularity is the lowest it reaches over the identity vertex
-order and seeded relabellings (tests/orders.py: the method leaves the
+order and seeded relabellings (oracle/orders.py: the method leaves the
 visiting order open, and weak SBM graphs end in optima that differ by more
 than 0.002 between orders).
 """
@@ -16,7 +16,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from orders import async_floor
+from oracle.orders import async_floor
 
 pytestmark = pytest.mark.gpu
 

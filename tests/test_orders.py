@@ -1,4 +1,4 @@
-"""CPU checks of the visiting-order reading of the ASYNC bound (tests/orders.py).
+"""CPU checks of the visiting-order reading of the ASYNC bound (oracle/orders.py).
 
 relabel() must be a pure renaming: modularity of a partition, the total
 weight and the degree multiset are unchanged, and renaming back restores the
@@ -12,7 +12,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from orders import oracle_q_orders, relabel
+from oracle.orders import oracle_q_orders, relabel
 
 
 @pytest.mark.parametrize("make", [lambda: gg.rmat(9, 8, seed=2), lambda: gg.random_small(40, 0.2, 5, self_loops=True),
