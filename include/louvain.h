@@ -168,6 +168,17 @@ typedef struct {
      * Results do not depend on it (the paper's "datatype for hashtable
      * values" experiment, Section 4.3, made exact). */
     int32_t table_values_64;
+    /* 1 = device-driven iterations: the tolerance test of Alg. 1 (per graph in
+     * a batch), the next queue's sizes and the end of a pass's local moving
+     * are decided on the device after each iteration, and the host enqueues
+     * the iterations of a pass in chunks (2, 4, 8, ...) with one readback per
+     * chunk instead of one per iteration; launches are sized for the pass's
+     * largest queue and those after the pass's end return at once.  ASYNC
+     * slices: every iteration of a pass uses the slice count of its first
+     * (min(async_slices, nonisolated / async_slice_min)).  Results: SYNC as
+     * with 0.  Not with the LEARNED pruner, sample recording or an
+     * iteration trace (LOUVAIN_ERR_INVALID).  0 = host-driven (default). */
+    int32_t device_loop;
 } louvain_params;
 
 /* Per-run counters, filled by louvain_get_stats after louvain_run. */
@@ -186,6 +197,7 @@ typedef struct {
     int64_t communities_per_pass[32];
     int64_t sweeps;             /* LEARNED: iterations that evaluated every vertex */
     int64_t pruned;             /* LEARNED: flagged vertices skipped by the MLP */
+    int64_t host_syncs;         /* times louvain_run waited for the stream */
 } louvain_stats;
 
 /* Per-kernel timing record (profiling mode). */

@@ -55,7 +55,8 @@ class LouvainParams(ctypes.Structure):
                 ("guard_tolerance", ctypes.c_int32), ("async_slice_min", ctypes.c_int32),
                 ("async_hub_groups", ctypes.c_int32), ("async_min_label", ctypes.c_int32),
                 ("pruner_weights", ctypes.c_void_p), ("pruner_threshold", ctypes.c_double),
-                ("async_interleave", ctypes.c_int32), ("table_values_64", ctypes.c_int32)]
+                ("async_interleave", ctypes.c_int32), ("table_values_64", ctypes.c_int32),
+                ("device_loop", ctypes.c_int32)]
 
 
 class LouvainStats(ctypes.Structure):
@@ -64,7 +65,7 @@ class LouvainStats(ctypes.Structure):
                 ("arcs_scanned", ctypes.c_int64), ("distinct_scanned", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("ms_move", ctypes.c_double), ("ms_aggregate", ctypes.c_double),
                 ("iterations_per_pass", ctypes.c_int32 * 32), ("communities_per_pass", ctypes.c_int64 * 32),
-                ("sweeps", ctypes.c_int64), ("pruned", ctypes.c_int64)]
+                ("sweeps", ctypes.c_int64), ("pruned", ctypes.c_int64), ("host_syncs", ctypes.c_int64)]
 
 
 class LouvainKernelStat(ctypes.Structure):

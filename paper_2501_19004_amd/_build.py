@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(OUT_DIR, "liblouvain_hip.so")
-SOURCES = ["lv_scan.hip", "lv_move.hip", "lv_aggr.hip", "lv_learn.hip", "lv_batch.hip", "lv_api.cpp"]
+SOURCES = ["lv_scan.hip", "lv_move.hip", "lv_aggr.hip", "lv_learn.hip", "lv_batch.hip", "lv_iter.hip", "lv_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code (the learned

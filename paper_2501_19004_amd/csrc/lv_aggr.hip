@@ -730,9 +730,9 @@ void bucketize_communities(int64_t ncom, const int64_t* hoff, int64_t bound_cap,
     hipMemsetAsync(rowlen, 0, (size_t)(ncom + 1) * sizeof(int32_t), s);
     const int64_t nb = bucket_blocks(ncom);
     AggBucket bf{hoff, bound_cap, B};
-    k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, ncom, blkcnt, nb);
+    k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, ncom, blkcnt, nb, nullptr);
     scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
-    k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, ncom, blkoff, nb, out);
+    k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, ncom, blkoff, nb, out, nullptr);
     k_bucket_totals<<<1, 32, 0, s>>>(blkoff, nb, NB, totals);
 }
 

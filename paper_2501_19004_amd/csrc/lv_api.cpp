@@ -47,10 +47,10 @@ struct Layout {
     size_t used, newid, cnt, coff, cursor, members, cdeg, hoff, cbucket, alist, rowlen;
     size_t hidx, hw, sup_off, sup_idx, sup_w, pool_keys, pool_vals, scan;
     size_t md, mpos, bnch, bchpre, bitmaps, gdec, blkcnt, blkoff;
-    size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots, hpart;
+    size_t f_own, f_adv, f_moved, f_nm, hcnt, hslots, hpart, dit, dshare;
     int64_t part_cap;
     // batched runs (count graphs; absent for a single graph)
-    size_t gid[2], gid0, Wg, gact, Sg, Pg, gsweep, gany, gcnt, cmin, vbase, gq, segcnt, segstart, prefall;
+    size_t gid[2], gid0, Wg, gact, Sg, Pg, gsweep, gany, gcnt, cmin, vbase, gq, segcnt, segstart, prefall, lig;
     int64_t bitmap_words;
     int64_t pool_entries;
     size_t total;
@@ -61,6 +61,8 @@ bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
     auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes > 0 ? bytes : 1); return at; };
     const size_t N = (size_t)n, M = (size_t)m;
     L->ctl = take(sizeof(Ctl));
+    L->dit = take(sizeof(DevIter));
+    L->dshare = take((size_t)NB_MOVE * std::max(1, slices) * 8);  // slice table of device-driven iterations
     L->seg = take(32 * sizeof(int64_t));
     L->C = take(N * 4);
     L->Cp = take(N * 4);
@@ -123,6 +125,7 @@ bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
         L->segcnt = take((size_t)NB_MOVE * G * 4);
         L->segstart = take((size_t)NB_MOVE * (G + 1) * 4);
         L->prefall = take((size_t)NB_MOVE * S * (G + 1) * 4);
+        L->lig = take(G * 4);     // per graph: iterations of the pass (device-driven iterations)
     }
     L->scan = take(scan_scratch_bytes(std::max(n, count) + 2));
     L->gdec = take(N * 4);
@@ -201,6 +204,7 @@ struct louvain_s {
     int64_t smp_cap = 0;
     int32_t smp_rate = 0;
     int64_t smp_count = 0;
+    int64_t syncs = 0;         // host waits on the stream during the current run
 
     template <typename T>
     T* at(size_t off) { return (T*)(ws + off); }
@@ -248,8 +252,16 @@ void timed(louvain_t* h, int kind, int64_t bytes, Fn&& fn) {
     h->recs.push_back({kind, a, b, bytes});
 }
 
+// Waits for the stream, counted (louvain_stats.host_syncs).
+louvain_status sync_stream(louvain_t* h) {
+    h->syncs++;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LOUVAIN_OK;
+}
+
 louvain_status readback(louvain_t* h, void* dst, const void* src, size_t bytes) {
     if (bytes == 0) return LOUVAIN_OK;
+    h->syncs++;
     if (bytes <= (1 << 20)) {
         HIPCHK(h, hipMemcpyAsync(h->pinned, src, bytes, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -401,8 +413,10 @@ louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t
          p->pruner != LOUVAIN_PRUNE_LEARNED) ||
         (p->guard_tolerance != 0 && p->guard_tolerance != 1) ||
         (p->table_values_64 != 0 && p->table_values_64 != 1) || p->async_slices < 0 || p->async_slice_min < 0 ||
-        p->async_hub_groups < 0)
+        p->async_hub_groups < 0 || (p->device_loop != 0 && p->device_loop != 1))
         return fail(nullptr, LOUVAIN_ERR_INVALID, "invalid parameter value");
+    if (p->device_loop && p->pruner == LOUVAIN_PRUNE_LEARNED)
+        return fail(nullptr, LOUVAIN_ERR_INVALID, "device_loop does not run the learned pruner");
     if (p->pruner == LOUVAIN_PRUNE_LEARNED && !p->pruner_weights)
         return fail(nullptr, LOUVAIN_ERR_INVALID, "the learned pruner needs pruner_weights");
     if (p->pruner_threshold != p->pruner_threshold)
@@ -615,6 +629,7 @@ louvain_status Runner::run() {
     void* scan = at<void>(Y.scan);
 
     memset(&H->st, 0, sizeof(H->st));
+    H->syncs = 0;
     H->smp_count = 0;
     H->recs.clear();
     H->evnext = 0;
@@ -660,17 +675,24 @@ louvain_status Runner::run() {
     // the next upload, so a pageable or shared one is waited for)
     auto upload_bytes = [&](uint8_t* dev, const std::vector<uint8_t>& src) -> louvain_status {
         if (nbg <= (1 << 16)) {
-            HIPCHK(H, hipStreamSynchronize(s));  // the previous upload has left the staging buffer
+            if ((st = sync_stream(H)) != LOUVAIN_OK) return st;  // the previous upload has left the staging buffer
             memcpy(H->pinned_up, src.data(), (size_t)nbg);
             HIPCHK(H, hipMemcpyAsync(dev, H->pinned_up, (size_t)nbg, hipMemcpyHostToDevice, s));
-            if (!H->stage_owned) HIPCHK(H, hipStreamSynchronize(s));
+            if (!H->stage_owned && (st = sync_stream(H)) != LOUVAIN_OK) return st;
         } else {
             HIPCHK(H, hipMemcpyAsync(dev, src.data(), (size_t)nbg, hipMemcpyHostToDevice, s));
-            HIPCHK(H, hipStreamSynchronize(s));
+            if ((st = sync_stream(H)) != LOUVAIN_OK) return st;
         }
         return LOUVAIN_OK;
     };
     auto upload_act = [&]() -> louvain_status { return upload_bytes(gact_dev, act); };
+    // device-driven iterations: the tests between iterations run in k_iter_end
+    const bool devloop = P.device_loop != 0;
+    if (devloop && (learn || H->itfn))
+        return fail(H, LOUVAIN_ERR_INVALID,
+                    "device_loop runs take no learned pruner, sample recording or iteration trace");
+    DevIter* dit = devloop ? at<DevIter>(Y.dit) : nullptr;
+    int32_t* lig_dev = devloop && batch ? at<int32_t>(Y.lig) : nullptr;
 
     for (int pass = 0; P.max_passes <= 0 || pass < P.max_passes; pass++) {
         const int64_t n = L.n;
@@ -744,6 +766,47 @@ louvain_status Runner::run() {
         const int mode = sync ? 0 : (P.async_coherent ? 2 : 1);
         bool sweep = learned;          // LEARNED: iteration 0 is a sweep
         int64_t smp_lo = 0, smp_hi = 0;  // samples recorded for the current iteration
+        // device-driven iterations: the host uses the pass's bucket sizes as
+        // launch bounds (counts/csegs stay those of iteration 0) and reads the
+        // pass's state back after chunks of 2, 4, 8, ... iterations
+        int32_t chunk_end = 0, chunk_len = 2;
+        std::vector<int32_t> seg_ub;  // batched slices: per bucket, a bound on any slice's entries
+        int32_t* dshare = devloop ? at<int32_t>(Y.dshare) : nullptr;
+        // ASYNC slices of iteration t: at most async_slices, at least
+        // async_slice_min queued vertices per slice (device-driven: counted on
+        // the pass's first queue, for every iteration of the pass)
+        auto slices_of = [&](int t, int64_t queued) {
+            const bool slice_now = P.async_slice_iters <= 0 || t < P.async_slice_iters;
+            const int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
+            return (int)std::max<int64_t>(1, std::min<int64_t>(ns, queued / std::max(1, P.async_slice_min)));
+        };
+        auto interleaved = [&](int ns) { return !sync && P.async_interleave && ns > 1 ? 1 : 0; };
+        if (devloop) {
+            const int ns0 = slices_of(0, nonisolated);
+            launch_iter_setup(dit, ctl()->bcount, NBT, P.max_iterations, dshare, ns0, interleaved(ns0), s);
+            if (batch) fill_i32(lig_dev, P.max_iterations, nbg, s);
+            chunk_end = std::min(P.max_iterations, chunk_len);
+        }
+        // profiling: algorithmic bytes of the move launches since the last
+        // call, per bucket, from the run's cumulative counters hc->bstat
+        auto attribute_move_bytes = [&](const Ctl* hc) {
+            for (int b = 0; b < NBT; b++) {
+                u64 cur[5];
+                for (int q = 0; q < 5; q++) {
+                    cur[q] = 0;
+                    for (int k = 0; k < STRIPES; k++) cur[q] += hc->bstat[q][b][k];
+                }
+                const u64 de = cur[0] - prev_b[0][b];
+                if (de) {
+                    const int64_t bytes = move_alg_bytes(LM, de, cur[1] - prev_b[1][b], cur[2] - prev_b[2][b],
+                                                         cur[3] - prev_b[3][b], cur[4] - prev_b[4][b], sync, learn);
+                    const int kind = b < 4 ? K_MOVE_FUSED : (b == 4 ? K_MOVE4 : K_MOVE_HUB);
+                    for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
+                        if (r->kind == kind) { r->bytes += bytes; break; }
+                }
+                for (int q = 0; q < 5; q++) prev_b[q][b] = cur[q];
+            }
+        };
         // learned pruner (or sample recording): features and MLP over the
         // vertices flagged by iteration t, then the queue of iteration t + 1
         // from the kept flags (vertices of stopped graphs are left out)
@@ -785,7 +848,7 @@ louvain_status Runner::run() {
                 });
             HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
             HIPCHK(H, hipMemcpyAsync(&hc->nsamples, &ctl()->nsamples, sizeof(u64), hipMemcpyDeviceToHost, s));
-            HIPCHK(H, hipStreamSynchronize(s));
+            if ((st = sync_stream(H)) != LOUVAIN_OK) return st;
             *itp = sum_iter(*hc);
             H->smp_count = std::min<int64_t>((int64_t)hc->nsamples, H->smp_cap);
             smp_lo = before;
@@ -803,14 +866,24 @@ louvain_status Runner::run() {
         };
         for (int t = 0; t < P.max_iterations; t++) {
             const int pl = P.pick_less > 0 && ((t + P.pick_less / 2) % P.pick_less) == 0;
-            HIPCHK(H, hipMemsetAsync(ctl(), 0, CTL_ITER_BYTES, s));
-            if (learn) HIPCHK(H, hipMemsetAsync(f_nm, 0, (size_t)n * 4, s));
-            if (batch) HIPCHK(H, hipMemsetAsync(Sg_dev, 0, (size_t)nbg * 16, s));
-            if (Pg_dev) HIPCHK(H, hipMemsetAsync(Pg_dev, 0, (size_t)nbg * 8, s));
             const uint32_t stamp_next = ++H->stamp;  // unique tag of this iteration
             uint8_t* fnext = flags + (size_t)(stamp_next & 1) * (size_t)n0;
             const uint8_t* fcur = flags + (size_t)((stamp_next + 1) & 1) * (size_t)n0;
-            if (prune) HIPCHK(H, hipMemsetAsync(fnext, 0, (size_t)n, s));
+            if (devloop) {
+                // one zeroing launch, which does nothing once the pass has ended
+                ZeroRanges z{};
+                z.p[0] = ctl();
+                z.bytes[0] = (int64_t)CTL_ITER_BYTES;
+                if (batch) { z.p[1] = Sg_dev; z.bytes[1] = nbg * 16; }
+                if (prune) { z.p[2] = fnext; z.bytes[2] = n; }
+                launch_zero_ranges(dit, z, s);
+            } else {
+                HIPCHK(H, hipMemsetAsync(ctl(), 0, CTL_ITER_BYTES, s));
+                if (learn) HIPCHK(H, hipMemsetAsync(f_nm, 0, (size_t)n * 4, s));
+                if (batch) HIPCHK(H, hipMemsetAsync(Sg_dev, 0, (size_t)nbg * 16, s));
+                if (Pg_dev) HIPCHK(H, hipMemsetAsync(Pg_dev, 0, (size_t)nbg * 8, s));
+                if (prune) HIPCHK(H, hipMemsetAsync(fnext, 0, (size_t)n, s));
+            }
             if (sweep) {
                 H->st.sweeps++;
             } else if (batch && learned) {
@@ -856,9 +929,11 @@ louvain_status Runner::run() {
             a.f_adv = f_adv;
             a.f_moved = f_moved;
             a.f_nm = f_nm;
+            a.dit = dit;
+            a.dshare = dshare;
             // hubs: chunked inserts, one decision per hub, chunked stamping, for
             // the static hub positions [s_lo, s_hi) whose tables share the pool
-            const bool hubs_now = nhub > 0 && counts[NB_MOVE] > 0;
+            const bool hubs_now = nhub > 0 && (devloop || counts[NB_MOVE] > 0);
             auto hubs_range = [&](int32_t s_lo, int32_t s_hi, bool decide_phase, bool mark_phase) {
                 a.bucket = NB_MOVE;
                 for (auto& gr : hub_groups) {
@@ -895,9 +970,7 @@ louvain_status Runner::run() {
             // every bucket), at least async_slice_min queued vertices per slice.
             int64_t queued = 0;
             for (int b = 0; b < NBT; b++) queued += counts[b];
-            const bool slice_now = P.async_slice_iters <= 0 || t < P.async_slice_iters;
-            int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
-            ns = (int)std::max<int64_t>(1, std::min<int64_t>(ns, queued / std::max(1, P.async_slice_min)));
+            const int ns = slices_of(t, queued);
             // hub groups: group k covers the static hub positions [k*nhub/hg, (k+1)*nhub/hg)
             // and runs with slice due(k) = (k+1)*ns/hg - 1
             const int hg = (!sync && P.async_hub_groups > 0) ? std::min(P.async_hub_groups, ns) : ns;
@@ -910,29 +983,43 @@ louvain_status Runner::run() {
             int32_t* prefall = segmented ? at<int32_t>(Y.prefall) : nullptr;
             std::vector<int32_t> segtot;
             if (segmented) {
-                HIPCHK(H, hipMemsetAsync(segcnt, 0, (size_t)NB_MOVE * nbg * 4, s));
+                if (devloop) {
+                    ZeroRanges z{};
+                    z.p[0] = segcnt;
+                    z.bytes[0] = (int64_t)NB_MOVE * nbg * 4;
+                    launch_zero_ranges(dit, z, s);
+                } else {
+                    HIPCHK(H, hipMemsetAsync(segcnt, 0, (size_t)NB_MOVE * nbg * 4, s));
+                }
                 for (int b = 0; b < NB_MOVE; b++)
-                    launch_seg_count(cur_list + csegs[b], counts[b], gid, segcnt + (int64_t)b * nbg, s);
+                    launch_seg_count(devloop ? cur_list : cur_list + csegs[b], counts[b], gid,
+                                     segcnt + (int64_t)b * nbg, s, dit, b);
                 for (int b = 0; b < NB_MOVE; b++)
                     scan_i32_to_i32(segcnt + (int64_t)b * nbg, segstart + (int64_t)b * (nbg + 1), nbg, scan, s);
                 launch_slice_prefix(segcnt, NB_MOVE, nbg, ns, prefall, s);
-                std::vector<int32_t> hseg((size_t)NB_MOVE * nbg);
-                if ((st = readback(H, hseg.data(), segcnt, hseg.size() * 4)) != LOUVAIN_OK) return st;
-                segtot.assign((size_t)NB_MOVE * ns, 0);
-                for (int b = 0; b < NB_MOVE; b++)
-                    for (int64_t g = 0; g < nbg; g++) {
-                        const int64_t len = hseg[(size_t)b * nbg + g];
-                        if (!len) continue;
-                        for (int k = 0; k < ns; k++)
-                            segtot[(size_t)b * ns + k] += (int32_t)(len * (k + 1) / ns - len * k / ns);
-                    }
+                if (!devloop || t == 0) {
+                    std::vector<int32_t> hseg((size_t)NB_MOVE * nbg);
+                    if ((st = readback(H, hseg.data(), segcnt, hseg.size() * 4)) != LOUVAIN_OK) return st;
+                    segtot.assign((size_t)NB_MOVE * ns, 0);
+                    seg_ub.assign(NB_MOVE, 0);
+                    for (int b = 0; b < NB_MOVE; b++)
+                        for (int64_t g = 0; g < nbg; g++) {
+                            const int64_t len = hseg[(size_t)b * nbg + g];
+                            if (!len) continue;
+                            for (int k = 0; k < ns; k++)
+                                segtot[(size_t)b * ns + k] += (int32_t)(len * (k + 1) / ns - len * k / ns);
+                            // a later queue holds at most len of graph g's entries: at most
+                            // ceil(len / ns) of them in any slice
+                            seg_ub[b] += (int32_t)((len + ns - 1) / ns);
+                        }
+                }
                 a.seg_n = (int32_t)nbg;
                 a.seg_ns = ns;
             }
             for (int sl = 0; sl < ns; sl++) {
                 // entries of bucket b in this slice: contiguous share [lo, hi), or
                 // (interleaved) every ns-th entry from sl on
-                const bool inter = !sync && P.async_interleave && ns > 1;
+                const bool inter = interleaved(ns);
                 auto lo_of = [&](int b) { return inter ? 0 : (int32_t)((int64_t)counts[b] * sl / ns); };
                 auto hi_of = [&](int b) {
                     return inter ? (counts[b] > sl ? (counts[b] - sl + ns - 1) / ns : 0)
@@ -941,6 +1028,21 @@ louvain_status Runner::run() {
                 a.lstride = inter ? ns : 1;
                 a.lphase = inter ? sl : 0;
                 a.seg_k = sl;
+                a.slice = sl;
+                // bucket b's entries of this slice (device-driven: the queue's base
+                // and a bound on the count; the kernels find the true share)
+                auto share = [&](int b, const int32_t** lst, int32_t* cnt) {
+                    if (devloop) {
+                        *lst = cur_list;
+                        *cnt = segmented ? (t == 0 ? segtot[(size_t)b * ns + sl] : seg_ub[b])
+                                         : (int32_t)(((int64_t)counts[b] + ns - 1) / ns);
+                    } else {
+                        const int32_t lo = segmented ? 0 : lo_of(b);
+                        const int32_t hi = segmented ? segtot[(size_t)b * ns + sl] : hi_of(b);
+                        *lst = cur_list + csegs[b] + lo;
+                        *cnt = hi - lo;
+                    }
+                };
                 auto seg_rows = [&](int b, const int32_t** pre, const int32_t** st0, const int32_t** cnt) {
                     *pre = prefall + ((int64_t)b * ns + sl) * (nbg + 1);
                     *st0 = segstart + (int64_t)b * (nbg + 1);
@@ -956,23 +1058,21 @@ louvain_status Runner::run() {
                 FusedLists f{};
                 f.blk_pre[0] = 0;
                 for (int b = 0; b < 4; b++) {
-                    const int32_t lo = segmented ? 0 : lo_of(b);
-                    const int32_t hi = segmented ? segtot[(size_t)b * ns + sl] : hi_of(b);
-                    f.list[b] = cur_list + csegs[b] + lo;
-                    f.count[b] = hi - lo;
+                    share(b, &f.list[b], &f.count[b]);
                     if (segmented) seg_rows(b, &f.seg_pre[b], &f.seg_start[b], &f.seg_cnt[b]);
                     const int ng = 256 / MOVE_G[b];
                     f.blk_pre[b + 1] = f.blk_pre[b] + (f.count[b] + ng - 1) / ng;
                 }
                 if (f.blk_pre[4] > 0) timed(H, K_MOVE_FUSED, 0, [&] { launch_move_fused(LM, mode, a, f, s); });
                 {
-                    const int32_t lo = segmented ? 0 : lo_of(4);
-                    const int32_t hi = segmented ? segtot[(size_t)4 * ns + sl] : hi_of(4);
-                    if (hi > lo) {
+                    const int32_t* l4 = nullptr;
+                    int32_t c4 = 0;
+                    share(4, &l4, &c4);
+                    if (c4 > 0) {
                         a.bucket = 4;
                         MoveArgs a4 = a;
                         if (segmented) seg_rows(4, &a4.seg_pre, &a4.seg_start, &a4.seg_cnt);
-                        timed(H, K_MOVE4, 0, [&] { launch_move(LM, 4, mode, a4, cur_list + csegs[4] + lo, hi - lo, s); });
+                        timed(H, K_MOVE4, 0, [&] { launch_move(LM, 4, mode, a4, l4, c4, s); });
                     }
                 }
                 if (!P.bucket_order && hubs_now && h_hi > h_lo) hubs_range(h_lo, h_hi, true, !sync);
@@ -984,39 +1084,70 @@ louvain_status Runner::run() {
             if (learn) launch_learn_label(H->smp_buf, smp_lo, smp_hi, f_moved, stamp_next, s);
             if (prune && !learn)
                 timed(H, K_QUEUE, 0, [&] {
-                    bucketize_vertices(n, vb, fnext, 1, gid, gact_dev, blkcnt, blkoff, qnext, ctl()->qcount, scan, s);
+                    bucketize_vertices(n, vb, fnext, 1, gid, gact_dev, blkcnt, blkoff, qnext, ctl()->qcount, scan, s,
+                                       devloop ? &dit->halt : nullptr);
                 });
+            if (devloop) {
+                // the tests between iterations, on the device
+                IterEndArgs e{};
+                e.dit = dit;
+                e.ctl = ctl();
+                e.t = t;
+                e.may_end = sync || !pl;
+                e.prune = prune;
+                e.max_iterations = P.max_iterations;
+                e.nbt = NBT;
+                e.W = W;
+                e.tol_num = P.tol_num;
+                e.tol_den = P.tol_den;
+                e.tol_drop = P.tol_drop;
+                e.pass = pass;
+                e.nbg = batch ? nbg : 0;
+                e.Sg = Sg_dev;
+                e.Wg = Wg_dev;
+                e.gact = gact_dev;
+                e.lig = lig_dev;
+                e.dshare = dshare;
+                e.ns_next = slices_of(t + 1, nonisolated);
+                e.interleave = interleaved(e.ns_next);
+                launch_iter_end(e, s);
+                if (prune) {
+                    cur_list = qnext;
+                    qsel ^= 1;
+                }
+                if (t + 1 < chunk_end) continue;
+                // end of a chunk: one readback of the pass's state
+                Ctl* hc = (Ctl*)H->pinned;
+                DevIter* hd = (DevIter*)((char*)H->pinned + (1 << 19));
+                if (H->prof)
+                    HIPCHK(H, hipMemcpyAsync(&hc->bstat, &ctl()->bstat, sizeof(hc->bstat), hipMemcpyDeviceToHost, s));
+                HIPCHK(H, hipMemcpyAsync(hd, dit, sizeof(DevIter), hipMemcpyDeviceToHost, s));
+                if ((st = sync_stream(H)) != LOUVAIN_OK) return st;
+                if (H->prof) attribute_move_bytes(hc);
+                if (!hd->halt && t + 1 < P.max_iterations) {
+                    chunk_len *= 2;
+                    chunk_end = std::min(P.max_iterations, t + 1 + chunk_len);
+                    continue;
+                }
+                li = hd->halt ? hd->li : P.max_iterations;
+                H->st.iterations += hd->ran + hd->extra;
+                H->st.moves += (int64_t)hd->moves;
+                if (batch && (st = readback(H, li_g.data(), lig_dev, (size_t)nbg * 4)) != LOUVAIN_OK) return st;
+                break;
+            }
             // read back the iteration's striped totals
             Ctl* hc = (Ctl*)H->pinned;
             HIPCHK(H, hipMemcpyAsync(hc, ctl(), CTL_ITER_BYTES, hipMemcpyDeviceToHost, s));
             if (H->prof) HIPCHK(H, hipMemcpyAsync(&hc->bstat, &ctl()->bstat, sizeof(hc->bstat), hipMemcpyDeviceToHost, s));
             if (batch) HIPCHK(H, hipMemcpyAsync(hS.data(), Sg_dev, (size_t)nbg * 16, hipMemcpyDeviceToHost, s));
             if (Pg_dev) HIPCHK(H, hipMemcpyAsync(hP.data(), Pg_dev, (size_t)nbg * 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(H, hipStreamSynchronize(s));
+            if ((st = sync_stream(H)) != LOUVAIN_OK) return st;
             IterTotals it = sum_iter(*hc);
             const unsigned __int128 S = it.S;
             H->st.iterations++;
             H->st.moves += (int64_t)it.moves;
             // algorithmic bytes of this iteration's move launches, per bucket
-            if (H->prof) {
-                for (int b = 0; b < NBT; b++) {
-                    u64 cur[5];
-                    for (int q = 0; q < 5; q++) {
-                        cur[q] = 0;
-                        for (int k = 0; k < STRIPES; k++) cur[q] += hc->bstat[q][b][k];
-                    }
-                    const u64 de = cur[0] - prev_b[0][b];
-                    if (de) {
-                        const int64_t bytes = move_alg_bytes(LM, de, cur[1] - prev_b[1][b], cur[2] - prev_b[2][b],
-                                                             cur[3] - prev_b[3][b], cur[4] - prev_b[4][b], sync,
-                                                             learn);
-                        const int kind = b < 4 ? K_MOVE_FUSED : (b == 4 ? K_MOVE4 : K_MOVE_HUB);
-                        for (auto r = H->recs.rbegin(); r != H->recs.rend(); ++r)
-                            if (r->kind == kind) { r->bytes += bytes; break; }
-                    }
-                    for (int q = 0; q < 5; q++) prev_b[q][b] = cur[q];
-                }
-            }
+            if (H->prof) attribute_move_bytes(hc);
             if (H->itfn) {
                 hcp.resize(n);
                 hsig.resize(n);
@@ -1425,7 +1556,7 @@ louvain_status Runner::run() {
         for (int32_t x : H->b_passes) mp = std::max(mp, x);
         H->st.passes = mp;
     }
-    HIPCHK(H, hipStreamSynchronize(s));
+    if ((st = sync_stream(H)) != LOUVAIN_OK) return st;
     H->st.communities = H->ncom;
     return LOUVAIN_OK;
 }
@@ -1457,6 +1588,7 @@ louvain_status finish_run(louvain_t* h, louvain_status st, double ms) {
                 h->st.distinct_scanned += (int64_t)c.bstat[2][b][k];
             }
     }
+    h->st.host_syncs = h->syncs;
     h->ran = true;
     return LOUVAIN_OK;
 }
@@ -1474,6 +1606,7 @@ louvain_status louvain_run(louvain_t* h) {
     Runner r(h);
     louvain_status st = r.run();
     (void)hipEventRecord(e1, h->stream);
+    h->syncs++;
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);

@@ -156,8 +156,17 @@ __global__ void __launch_bounds__(BT) k_mod_terms_batch(int64_t ncom, const int3
 
 // Per-graph counts of one bucket's queue segment (id order, so graphs form
 // runs): segcnt[g] += entries of graph g.
+// Device-driven iterations (dit): list is the queue's base; bucket b's
+// entries and their number come from dit, len is the launch's bound.
 __global__ void __launch_bounds__(BT) k_seg_count(const int32_t* __restrict__ list, int64_t len,
-                                                  const int32_t* __restrict__ gid, int32_t* __restrict__ segcnt) {
+                                                  const int32_t* __restrict__ gid, int32_t* __restrict__ segcnt,
+                                                  const DevIter* __restrict__ dit, int b) {
+    if (dit) {
+        if (dit->halt) return;
+        list += dit->seg[b];
+        len = dit->cnt[b];
+        if ((int64_t)blockIdx.x * BT >= len) return;
+    }
     const int64_t j = (int64_t)blockIdx.x * BT + threadIdx.x;
     const int32_t key = j < len ? gid[list[j]] : -1;
     __shared__ int32_t s_k[BT];
@@ -216,8 +225,9 @@ __global__ void __launch_bounds__(1024) k_slice_prefix(const int32_t* __restrict
 
 }  // namespace
 
-void launch_seg_count(const int32_t* list, int64_t len, const int32_t* gid, int32_t* segcnt, hipStream_t s) {
-    if (len > 0) k_seg_count<<<(unsigned)((len + BT - 1) / BT), BT, 0, s>>>(list, len, gid, segcnt);
+void launch_seg_count(const int32_t* list, int64_t len, const int32_t* gid, int32_t* segcnt, hipStream_t s,
+                      const DevIter* dit, int b) {
+    if (len > 0) k_seg_count<<<(unsigned)((len + BT - 1) / BT), BT, 0, s>>>(list, len, gid, segcnt, dit, b);
 }
 
 void launch_slice_prefix(const int32_t* segcnt, int nbt, int64_t count, int ns, int32_t* prefall, hipStream_t s) {

@@ -52,10 +52,12 @@ __device__ __forceinline__ void block_excl_scan_nb(int32_t (&v)[NB], int32_t (&t
 }
 
 // bucket functor: __device__ int operator()(int64_t item) const, returns a
-// bucket in [0, NB) or a value >= NB for "no bucket".
+// bucket in [0, NB) or a value >= NB for "no bucket".  halt (may be NULL):
+// the launch does nothing when *halt != 0.
 template <int NB, typename BF>
 __global__ void __launch_bounds__(BK_TPB) k_bucket_count(BF bf, int64_t n, int32_t* __restrict__ blkcnt,
-                                                         int64_t nblocks) {
+                                                         int64_t nblocks, const int32_t* __restrict__ halt) {
+    if (halt && *halt) return;
     int32_t cnt[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) cnt[b] = 0;
@@ -79,7 +81,9 @@ __global__ void __launch_bounds__(BK_TPB) k_bucket_count(BF bf, int64_t n, int32
 
 template <int NB, typename BF>
 __global__ void __launch_bounds__(BK_TPB) k_bucket_fill(BF bf, int64_t n, const int32_t* __restrict__ blkoff,
-                                                        int64_t nblocks, int32_t* __restrict__ out) {
+                                                        int64_t nblocks, int32_t* __restrict__ out,
+                                                        const int32_t* __restrict__ halt) {
+    if (halt && *halt) return;
     int32_t cnt[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) cnt[b] = 0;

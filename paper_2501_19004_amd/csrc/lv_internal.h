@@ -41,6 +41,22 @@ struct LevelView {
     LevelTypes t{};
 };
 
+// Device-driven iterations (louvain_params.device_loop): the host enqueues a
+// pass's iterations without waiting for each one; every launch is sized for
+// the pass's largest queue and reads the true queue sizes, and whether the
+// pass has ended, from this record, which k_iter_end updates after each
+// iteration with the method's convergence tests.
+struct DevIter {
+    int32_t halt;                  // 1: local moving of this pass has ended; later launches do nothing
+    int32_t li;                    // the pass's iteration count (max_iterations until it ends earlier)
+    int32_t ran;                   // iterations that ran
+    int32_t extra;                 // iterations counted without running (nothing flagged: S = 0)
+    int32_t cnt[MAX_BUCKETS];      // current queue: entries per bucket ...
+    int32_t seg[MAX_BUCKETS + 1];  // ... and where each bucket's entries start
+    int32_t pad;
+    u64 moves;                     // moves applied in the pass
+};
+
 // Per-iteration arguments of the local-moving kernels.
 // Partial best candidate of one hub-decide block (a slice of the hub's
 // occupied slots); the hub's last block combines them.
@@ -105,6 +121,14 @@ struct MoveArgs {
     i64* f_adv;              // K_{v->d*} - K_{v->C'[v]} at v's last evaluation
     uint32_t* f_moved;       // tag of the last iteration in which v moved
     int32_t* f_nm;           // moved neighbours of v in this iteration (cleared before it)
+    // device-driven iterations (nullptr: the host passes exact lists and
+    // counts): list arguments are the queue's base and counts are launch
+    // bounds; slice `slice` of bucket b starts at dshare[2 * (slice * NB_MOVE
+    // + b)] and holds the next entry's count of entries (batched slices:
+    // dit->seg[b] and seg_pre[seg_n])
+    const DevIter* dit;
+    const int32_t* dshare;
+    int32_t slice;
 };
 
 // Learned-pruner filter of the next iteration's queue (lv_learn.hip).
@@ -168,10 +192,12 @@ void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int
 // Ordered partition of the level's vertices into NB_MOVE+1 bucket segments
 // (all vertices with arcs, or the flagged ones when use_flags); bucket totals
 // go to totals[0..NB_MOVE].  blkcnt/blkoff: (NB_MOVE+1) * bucket_blocks(n) (+1).
+// halt (may be NULL): when *halt != 0 at run time the count and fill
+// launches do nothing (device-driven iterations past the pass's end).
 void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags, const int32_t* gid,
                         const uint8_t* gact,
                         int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
-                        hipStream_t s);
+                        hipStream_t s, const int32_t* halt = nullptr);
 void launch_rowsum(const LevelView& L, int bucket, const int32_t* list, int32_t count, i64* K, i64* Sig, Ctl* ctl,
                    hipStream_t s);
 void launch_hub_caps(const LevelView& L, const int32_t* list, int32_t count, int64_t* caps, int64_t* nch,
@@ -196,8 +222,44 @@ void launch_mlp_loss_grad(const float* w, const float* S, int64_t count, int64_t
 void launch_adam(float* w, const float* g, float* m, float* v, float lr, float bc1, float bc2, hipStream_t s);
 // batched slices: per-(bucket, graph) segment counts of the queue, their
 // starts, and for every slice the per-graph slot prefixes
-void launch_seg_count(const int32_t* list, int64_t len, const int32_t* gid, int32_t* segcnt, hipStream_t s);
+// With dit (device-driven iterations): list is the queue's base, the bucket
+// b segment is read from dit and len is only the launch's upper bound.
+void launch_seg_count(const int32_t* list, int64_t len, const int32_t* gid, int32_t* segcnt, hipStream_t s,
+                      const DevIter* dit = nullptr, int b = 0);
 void launch_slice_prefix(const int32_t* segcnt, int nbt, int64_t count, int ns, int32_t* prefall, hipStream_t s);
+// ---- device-driven iterations (lv_iter.hip)
+// Up to 4 byte ranges zeroed by one launch (a kernel, so that the sequence
+// can be captured); nothing happens when dit->halt is set.
+struct ZeroRanges {
+    void* p[4];
+    int64_t bytes[4];
+};
+void launch_zero_ranges(const DevIter* dit, const ZeroRanges& z, hipStream_t s);
+// Slices of an iteration: dshare[2 * (k * NB_MOVE + b)] = start of slice k
+// of bucket b in the queue, dshare[... + 1] = its entries, for ns slices
+// (contiguous shares, or every ns-th entry with interleave).
+// Start of a pass: the queue is the pass's bucket lists (bcount), not halted.
+void launch_iter_setup(DevIter* dit, const int32_t* bcount, int nbt, int32_t max_iterations, int32_t* dshare,
+                       int ns, int interleave, hipStream_t s);
+// End of iteration t (see lv_iter.hip for the rules; they are the host
+// loop's).  thr: tolerance of the pass as tol_num, tol_den, tol_drop, pass.
+struct IterEndArgs {
+    DevIter* dit;
+    const Ctl* ctl;
+    int32_t t, may_end, prune, max_iterations, nbt;
+    i64 W;
+    int64_t tol_num, tol_den, tol_drop;
+    int32_t pass;
+    int64_t nbg;          // batched runs: graphs (0: single graph)
+    const u64* Sg;        // per-graph gain sums (lo, hi)
+    const u64* Wg;
+    uint8_t* gact;        // cleared for graphs that converge
+    int32_t* lig;         // per-graph iteration count of the pass
+    int32_t* dshare;      // slices of the next iteration: ns_next of them
+    int32_t ns_next, interleave;
+};
+void launch_iter_end(const IterEndArgs& e, hipStream_t s);
+
 // ---- batched runs (lv_batch.hip)
 void launch_gid_init(const int64_t* vbase, int64_t count, int64_t n, int32_t* gid, hipStream_t s);
 void launch_graph_weights(const LevelView& L, const int32_t* gid, u64* Wg, Ctl* ctl, hipStream_t s);

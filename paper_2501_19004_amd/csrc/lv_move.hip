@@ -438,6 +438,22 @@ __device__ __forceinline__ int64_t queue_entry(const MoveArgs& a, int64_t slot) 
     return e;
 }
 
+// Device-driven iterations: this launch's share of bucket b's queue (list is
+// the queue's base on entry); false once the pass has ended.
+__device__ __forceinline__ bool dev_share(const MoveArgs& a, const int32_t* seg_pre, int b, const int32_t*& list,
+                                          int32_t& count) {
+    if (a.dit->halt) return false;
+    if (seg_pre) {  // batched slices: the slice's slots over all graphs
+        list += a.dit->seg[b];
+        count = seg_pre[a.seg_n];
+        return true;
+    }
+    const int32_t* e = a.dshare + 2 * (a.slice * NB_MOVE + b);
+    list += e[0];
+    count = e[1];
+    return true;
+}
+
 // One block of a degree bucket: NG = BLOCK/G vertices, each evaluated by G
 // lanes with a CAP-slot table in LDS (keys/vals point at this block's LDS).
 template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE, bool WIDE>
@@ -729,11 +745,13 @@ template <typename OffT, int WK, typename AccT, int G, int CAP, int MODE, bool W
 __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, const int32_t* __restrict__ list,
                                                                 int32_t count) {
     constexpr int NG = (G > 256 ? G : 256) / G;
+    const int32_t* lst = list;
+    if (a.dit && (!dev_share(a, a.seg_pre, a.bucket, lst, count) || (int64_t)blockIdx.x * NG >= count)) return;
     __shared__ int32_t s_keys[NG * CAP];
     __shared__ AccT s_vals[NG * CAP];
     __shared__ uint16_t s_list[NG * CAP / 2];
     __shared__ MoveShm sh;
-    move_block<OffT, WK, AccT, G, CAP, MODE, WIDE>(a, list, count, blockIdx.x, a.bucket, s_keys, s_vals, s_list,
+    move_block<OffT, WK, AccT, G, CAP, MODE, WIDE>(a, lst, count, blockIdx.x, a.bucket, s_keys, s_vals, s_list,
                                                    sh);
 }
 
@@ -755,18 +773,25 @@ k_move_fused(MoveArgs a, FusedLists f) {
     aa.seg_pre = f.seg_pre[bk];
     aa.seg_start = f.seg_start[bk];
     aa.seg_cnt = f.seg_cnt[bk];
+    const int32_t* list = f.list[bk];
+    int32_t count = f.count[bk];
+    if (a.dit) {  // device-driven: blocks beyond the true share leave at once
+        const int ng = bk == 0 ? 256 / MOVE_G[0] : bk == 1 ? 256 / MOVE_G[1] : bk == 2 ? 256 / MOVE_G[2]
+                                                                                     : 256 / MOVE_G[3];
+        if (!dev_share(a, f.seg_pre[bk], bk, list, count) || blk * ng >= count) return;
+    }
     switch (bk) {
         case 0: {
             static_assert(MOVE_G[0] == 1, "bucket 0 is the lane-per-vertex path");
             using KeyT = typename std::conditional<WIDE, i128, i64>::type;
-            move_lanes<OffT, WK, MODE, KeyT>(aa, f.list[0], f.count[0], blk, 0, sh);
+            move_lanes<OffT, WK, MODE, KeyT>(aa, list, count, blk, 0, sh);
             break;
         }
         case 1: {
             constexpr int NG = 256 / MOVE_G[1];
             constexpr int TB = NG * MOVE_CAP[1];
             move_block<OffT, WK, AccT, MOVE_G[1], MOVE_CAP[1], MODE, WIDE>(
-                aa, f.list[1], f.count[1], blk, 1, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
+                aa, list, count, blk, 1, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
                 (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
         }
@@ -774,7 +799,7 @@ k_move_fused(MoveArgs a, FusedLists f) {
             constexpr int NG = 256 / MOVE_G[2];
             constexpr int TB = NG * MOVE_CAP[2];
             move_block<OffT, WK, AccT, MOVE_G[2], MOVE_CAP[2], MODE, WIDE>(
-                aa, f.list[2], f.count[2], blk, 2, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
+                aa, list, count, blk, 2, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
                 (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
         }
@@ -782,7 +807,7 @@ k_move_fused(MoveArgs a, FusedLists f) {
             constexpr int NG = 256 / MOVE_G[3];
             constexpr int TB = NG * MOVE_CAP[3];
             move_block<OffT, WK, AccT, MOVE_G[3], MOVE_CAP[3], MODE, WIDE>(
-                aa, f.list[3], f.count[3], blk, 3, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
+                aa, list, count, blk, 3, (int32_t*)dyn, (AccT*)(dyn + TB * 4),
                 (uint16_t*)(dyn + TB * (4 + sizeof(AccT))), sh);
             break;
         }
@@ -813,6 +838,7 @@ __device__ __forceinline__ int32_t owner_of(const int64_t* pre, int32_t n, int64
 
 template <typename OffT, int WK, typename AccT, int MODE>
 __global__ void __launch_bounds__(1024) k_hub_insert(MoveArgs a) {
+    if (a.dit && a.dit->halt) return;
     constexpr int G = 1024;
     constexpr int L2C = Log2<HUB_LCAP>::v;
     constexpr int PER = HUB_LCAP / G;
@@ -982,6 +1008,7 @@ __device__ __forceinline__ void hub_decide_block(const MoveArgs& a, int32_t h, i
 
 template <typename OffT, int WK, typename AccT, int MODE>
 __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
+    if (a.dit && a.dit->halt) return;
     constexpr int G = 1024;
     __shared__ i128 s_k128[G / WAVE];
     __shared__ i64 s_k64[G / WAVE];
@@ -1032,6 +1059,7 @@ __device__ __forceinline__ void hub_final_wave(const MoveArgs& a, int32_t h, int
 
 template <typename OffT, int MODE>
 __global__ void __launch_bounds__(256) k_hub_final(MoveArgs a) {
+    if (a.dit && a.dit->halt) return;
     const int lane = threadIdx.x % WAVE;
     const int32_t h = a.g_lo + (int32_t)((int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE);
     if (h >= a.g_hi) return;  // uniform per wave
@@ -1045,6 +1073,7 @@ __global__ void __launch_bounds__(256) k_hub_final(MoveArgs a) {
 
 template <typename OffT>
 __global__ void __launch_bounds__(1024) k_hub_mark(MoveArgs a) {
+    if (a.dit && a.dit->halt) return;
     const int32_t ng = a.g_hi - a.g_lo;
     const int64_t chunk_base = a.hch_pre[a.g_lo];
     const int32_t h = a.g_lo + owner_of(a.hch_pre + a.g_lo, ng, chunk_base, blockIdx.x);
@@ -1063,6 +1092,11 @@ __global__ void __launch_bounds__(1024) k_hub_mark(MoveArgs a) {
 // lane applies its own vertex's move; the wave then walks each mover's row.
 template <typename OffT>
 __global__ void __launch_bounds__(256) k_sync_apply(MoveArgs a, const int32_t* __restrict__ list, int64_t count) {
+    if (a.dit) {  // device-driven: the whole queue, of the size the last iteration left
+        if (a.dit->halt) return;
+        count = a.dit->seg[MAX_BUCKETS];
+        if ((int64_t)blockIdx.x * 256 >= count) return;
+    }
     const int lane = threadIdx.x % WAVE;
     const int64_t k = ((int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE) * WAVE + lane;
     const Graph<OffT, 0> g{(const OffT*)a.off, a.idx, nullptr};
@@ -1108,7 +1142,7 @@ void launch_classify(const LevelView& L, const Buckets& B, uint8_t* vbucket, int
 void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags, int use_flags, const int32_t* gid,
                         const uint8_t* gact,
                         int32_t* blkcnt, int32_t* blkoff, int32_t* out, int32_t* totals, void* scratch,
-                        hipStream_t s) {
+                        hipStream_t s, const int32_t* halt) {
     constexpr int NB = NB_MOVE + 1;
     const int64_t nb = bucket_blocks(n);
     if (n <= 0) {
@@ -1117,14 +1151,14 @@ void bucketize_vertices(int64_t n, const uint8_t* vbucket, const uint8_t* flags,
     }
     if (use_flags) {
         MarkBucket bf{vbucket, flags, gid, gact};
-        k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb);
+        k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb, halt);
         scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
-        k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out);
+        k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out, halt);
     } else {
         VBucket bf{vbucket};
-        k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb);
+        k_bucket_count<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkcnt, nb, halt);
         scan_i32_to_i32(blkcnt, blkoff, NB * nb, scratch, s);
-        k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out);
+        k_bucket_fill<NB><<<(unsigned)nb, BK_TPB, 0, s>>>(bf, n, blkoff, nb, out, halt);
     }
     k_bucket_totals<<<1, 32, 0, s>>>(blkoff, nb, NB, totals);
 }
