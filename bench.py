@@ -22,10 +22,15 @@ counts stored arcs (each undirected edge twice), as the paper does.  Legs:
     guard, the tolerance guard, and threshold 0 with the strict guard (flag
     pruning plus the same certifying sweeps: isolates what the MLP saves);
   - autotune: louvain_autotune over candidate degree thresholds;
+  - device_loop: device-driven iterations against the host-driven loop on
+    the workload and on the 1000-vertex planted partition;
   - batch: 4096 SBM graphs, vertex counts log-uniform in [200, 200000];
   - cpu_baseline: the sequential oracle on the host (one core), and the
     OpenMP CPU baseline on all host cores with a thread sweep, both on a
-    stated sample of the same recipe when the workload is beyond them.
+    stated sample of the same recipe when the workload is beyond them; the
+    batch's first graphs against the oracle's lowest Q over visiting orders.
+  - optional: --ablations (design-space experiments), --handoff (late-pass
+    handoff study).
 Prints one JSON line.
 
 Other workloads (--workload): rmat22, rmatS (S <= 24, edge factor 16),
@@ -213,6 +218,44 @@ def learned_leg(lv, torch, nnz, graph, mode, args, q_plain, dt_plain, wts, info)
     return legs
 
 
+def device_loop_leg(lv, torch, graph, nnz, mode, reps, dt_host, q_host, st_host):
+    """Device-driven iterations (device_loop = 1: the tests between
+    iterations run on the GPU, the host waits once per chunk of iterations)
+    against the host-driven loop, on this workload and on the 1000-vertex
+    planted partition (launch- and wait-bound): ms per run, modularity and
+    the host's waits on the stream per run."""
+    import graphgen as gg
+    off, idx, w = graph
+    L = lv.Louvain(off, idx, w, mode=mode, device_loop=1)
+    dt, q, st = timed_runs(L, reps, 1)
+    L.close()
+    del L
+    torch.cuda.empty_cache()
+    out = {"workload": {"host_driven": {"ms_per_step": round(dt_host * 1e3, 3), "value": round(nnz / dt_host / 1e6, 2),
+                                        "modularity": round(q_host, 6), "host_syncs": st_host.host_syncs,
+                                        "passes": st_host.passes, "iterations": st_host.iterations},
+                        "device_driven": {"ms_per_step": round(dt * 1e3, 3), "value": round(nnz / dt / 1e6, 2),
+                                          "modularity": round(q, 6), "host_syncs": st.host_syncs,
+                                          "passes": st.passes, "iterations": st.iterations},
+                        "speedup": round(dt_host / dt, 3)}}
+    gp = gg.planted_partition(seed=1)
+    o2, i2, w2 = lv.graph_tensors(gp, "cuda:0")
+    small = {}
+    for name, dl in (("host_driven", 0), ("device_driven", 1)):
+        L = lv.Louvain(o2, i2, w2, mode=mode, device_loop=dl)
+        d2, q2, s2 = timed_runs(L, 50, 5)
+        L.close()
+        small[name] = {"ms_per_step": round(d2 * 1e3, 3), "value": round(gp.nnz / d2 / 1e6, 2),
+                       "modularity": round(q2, 6), "host_syncs": s2.host_syncs, "passes": s2.passes,
+                       "iterations": s2.iterations}
+    small["speedup"] = round(small["host_driven"]["ms_per_step"] / small["device_driven"]["ms_per_step"], 3)
+    out["planted_1000"] = small
+    for k, v in out.items():
+        log(f"device loop {k}: host-driven {v['host_driven']['ms_per_step']} ms ({v['host_driven']['host_syncs']} "
+            f"waits), device-driven {v['device_driven']['ms_per_step']} ms ({v['device_driven']['host_syncs']} waits)")
+    return out
+
+
 def ablation_leg(lv, torch, graph, nnz, mode, reps):
     """The paper's GPU design-space experiments (Section 4.3) repeated on this
     workload: Pick-Less period (community swaps), the degree that switches a
@@ -315,9 +358,11 @@ def batch_graphs(count, nmax, threads):
 
 def batch_leg(lv, torch, args, wts=None):
     """4096 SBM graphs in one batched handle: ASYNC plain, ASYNC learned
-    (strict guard), and SYNC (the deterministic parity mode, timed for
-    reference: its quality is not Louvain's); per-graph ASYNC quality
-    against the sequential oracle on the first graphs."""
+    (strict guard), ASYNC with device-driven iterations, and SYNC host- and
+    device-driven (the deterministic parity mode, timed for reference: its
+    quality is not Louvain's).  Returns the leg results, the
+    first graphs and the ASYNC legs' per-graph Q on them, for the
+    CPU-baseline leg's comparison with the oracle."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -334,9 +379,11 @@ def batch_leg(lv, torch, args, wts=None):
     if wts is not None:
         legs.append((lv.ASYNC, "async_learned", dict(pruner=lv.PRUNE_LEARNED, pruner_weights=wts,
                                                      pruner_threshold=args.threshold, guard_tolerance=0)))
+    legs.append((lv.ASYNC, "async_device_loop", dict(device_loop=1)))
     legs.append((lv.SYNC, "sync_parity_mode", {}))
-    qo = None
+    legs.append((lv.SYNC, "sync_parity_mode_device_loop", dict(device_loop=1)))
     nchk = min(args.batch_check, len(graphs))
+    checks = {}
     for mode, name, extra in legs:
         L = lv.Louvain(off, idx, w, vbase=vbase, mode=mode, **extra)
         dt, _, st = timed_runs(L, args.aux_steps, 1)
@@ -347,7 +394,10 @@ def batch_leg(lv, torch, args, wts=None):
         torch.cuda.empty_cache()
         out[name] = {"value": round(na / dt / 1e6, 2), "unit": "M edges/s", "ms_per_step": round(dt * 1e3, 3),
                      "runs": args.aux_steps, "mean_modularity": round(float(q.mean()), 6),
-                     "max_passes": int(max(passes)), "max_iterations": int(max(iters))}
+                     "max_passes": int(max(passes)), "max_iterations": int(max(iters)), "host_syncs": st.host_syncs}
+        if name.endswith("_device_loop"):
+            base = name[:-len("_device_loop")]
+            out[name]["speedup_vs_host_driven"] = round(out[base]["ms_per_step"] / out[name]["ms_per_step"], 3)
         if name == "sync_parity_mode":
             out[name]["note"] = ("SYNC decides every vertex against the iteration's snapshot (bit-exact parity "
                                  "mode); on these graphs its modularity is far below ASYNC's, so this is a timing "
@@ -355,28 +405,35 @@ def batch_leg(lv, torch, args, wts=None):
         if name == "async_learned":
             out[name]["speedup_vs_async"] = round(out["async"]["ms_per_step"] / out[name]["ms_per_step"], 3)
             out[name]["dq_mean_vs_async"] = round(float(q.mean()) - out["async"]["mean_modularity"], 6)
-        if not args.no_cpu_baseline and mode == lv.ASYNC and nchk:
-            # per-graph quality against the sequential oracle: its identity
-            # order, and the lowest Q it reaches over that order and 8 seeded
-            # relabellings (the yardstick of the GPU tests: the method leaves
-            # the visiting order open)
-            if qo is None:
-                from oracle.orders import oracle_q_orders
-
-                def oq(gk):
-                    return oracle_q_orders(gk)
-                with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-                    qo = np.array(list(ex.map(oq, graphs[:nchk])))
-            d_id = q[:nchk] - qo[:, 0]
-            d_fl = q[:nchk] - qo.min(axis=1)
-            out[name]["dq_vs_oracle_first_graphs"] = {
-                "graphs": nchk, "identity_order": {"mean": round(float(d_id.mean()), 6),
-                                                   "min": round(float(d_id.min()), 6)},
-                "lowest_over_9_orders": {"mean": round(float(d_fl.mean()), 6), "min": round(float(d_fl.min()), 6),
-                                         "below_minus_0.002": int((d_fl < -0.002).sum())}}
+        if mode == lv.ASYNC and nchk:
+            checks[name] = q[:nchk].copy()
         log(f"batch {name}: {dt * 1e3:.2f} ms/run, {na / dt / 1e6:.1f} M arcs/s, mean Q {q.mean():.4f}")
     del off, idx, w
-    return out
+    return out, graphs[:nchk], checks
+
+
+def batch_quality_vs_oracle(out, graphs, checks, threads):
+    """CPU-baseline leg, batched part: per-graph Q of the GPU's ASYNC legs on
+    the first graphs against the sequential oracle -- its identity order, and
+    the lowest Q it reaches over that order and 8 seeded relabellings (the
+    yardstick of the GPU tests: the method leaves the visiting order open)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    from oracle.orders import oracle_q_orders
+    if not graphs or not checks:
+        return
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        qo = np.array(list(ex.map(oracle_q_orders, graphs)))
+    for name, q in checks.items():
+        d_id = q - qo[:, 0]
+        d_fl = q - qo.min(axis=1)
+        out[name]["dq_vs_oracle_first_graphs"] = {
+            "graphs": len(graphs), "identity_order": {"mean": round(float(d_id.mean()), 6),
+                                                      "min": round(float(d_id.min()), 6)},
+            "lowest_over_9_orders": {"mean": round(float(d_fl.mean()), 6), "min": round(float(d_fl.min()), 6),
+                                     "below_minus_0.002": int((d_fl < -0.002).sum())}}
 
 
 def cpu_baselines(args, workload_graph, q_gpu):
@@ -555,6 +612,7 @@ def main():
     L.close()
     del L
     torch.cuda.empty_cache()
+    devloop = device_loop_leg(lv, torch, (off, idx, w), nnz, mode, args.aux_steps, dt, q, st)
     ablations = ablation_leg(lv, torch, (off, idx, w), nnz, mode, args.aux_steps) if args.ablations else None
     handoff = handoff_leg(lv, torch, (off, idx, w), nnz, mode, dt, st.passes, args.aux_steps) if args.handoff else None
     learned = wts = None
@@ -565,11 +623,15 @@ def main():
         del off, idx, w
         torch.cuda.empty_cache()
     batch = None
+    batch_checked = ([], {})
     if not args.no_batch:
-        batch = batch_leg(lv, torch, args, wts)
+        batch, *batch_checked = batch_leg(lv, torch, args, wts)
     cpu = multicore = None
     if not args.no_cpu_baseline:
         cpu, multicore = cpu_baselines(args, g, q)
+        if batch is not None:
+            batch_quality_vs_oracle(batch, batch_checked[0], batch_checked[1],
+                                    max(1, min(16, os.cpu_count() or 1)))
 
     out = {
         "metric": METRIC,
@@ -599,6 +661,7 @@ def main():
         "learned_pruner": learned,
         "autotuned": tuned,
         "batch": batch,
+        "device_loop": devloop,
     }
     if ablations is not None:
         out["ablations"] = ablations
