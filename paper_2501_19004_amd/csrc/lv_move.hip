@@ -306,8 +306,8 @@ __device__ __forceinline__ Best<KeyT> scan_table(const MoveArgs& a, i64 W, const
 // The move of vertex i (community c) from its best candidate: the gain
 // against staying, Pick-Less, and (concurrent modes) the minimum-label rule.
 template <int MODE, typename KeyT>
-__device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bool active, int32_t c, i64 Ki,
-                                                    const Best<KeyT>& b, i64 Sc) {
+__device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bool active, int32_t i, int32_t c,
+                                                    i64 Ki, const Best<KeyT>& b, i64 Sc) {
     Decision r{-1, 0, b.kic, 0, b.nd, b.bd != EMPTY_KEY ? b.bv : 0, 0};
     if (active && b.bd != EMPTY_KEY) {
         const KeyT stay = (KeyT)W * b.kic - (KeyT)Ki * (Sc - Ki);
@@ -315,6 +315,9 @@ __device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bo
         r.positive = gk > 0;
         bool ok = gk > 0 && (!a.pl || b.bd < c);
         if constexpr (MODE != M_SYNC) {
+            // a positive move refused by Pick-Less is still pending: i stays
+            // queued for the next iteration, as a mover's neighbours are
+            if (gk > 0 && !ok && a.prune) a.fnext[i] = 1;
             // i alone in c, d a single-vertex community of larger id: let d's vertex come to c instead
             if (ok && a.min_label && b.bd > c && Sc == Ki && ld_c<MODE>(&a.Cp[b.bd]) == b.bd &&
                 ld_s<MODE>(&a.Sig[b.bd]) == a.K[b.bd])
@@ -330,10 +333,10 @@ __device__ __forceinline__ Decision finish_decision(const MoveArgs& a, i64 W, bo
 template <int G, int MODE, typename KeyT, typename AccT>
 __device__ __forceinline__ Decision decide(const MoveArgs& a, i64 W, const int32_t* keys, const AccT* vals, int64_t cap,
                                            int lane, bool active, int32_t c, i64 Ki, i64 Sc, KeyT* s_k, int32_t* s_d,
-                                           i64* s_v, i64* s_t, const uint16_t* list, int64_t nlist) {
+                                           i64* s_v, i64* s_t, const uint16_t* list, int64_t nlist, int32_t i) {
     const Best<KeyT> b = scan_table<G, MODE, KeyT, AccT, uint16_t>(a, W, keys, vals, cap, lane, c, Ki, s_k, s_d, s_v,
                                                                    s_t, list, nlist);
-    return finish_decision<MODE, KeyT>(a, W, active, c, Ki, b, Sc);
+    return finish_decision<MODE, KeyT>(a, W, active, i, c, Ki, b, Sc);
 }
 
 // ASYNC move with validation: Sigma of the target is updated by an atomic
@@ -527,10 +530,10 @@ __device__ __forceinline__ void move_block(const MoveArgs& a, const int32_t* __r
     Decision dcs;
     if constexpr (!WIDE)
         dcs = decide<G, MODE, i64, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k64, sh.d, sh.v, sh.t,
-                                         occ, nocc);
+                                         occ, nocc, i);
     else
         dcs = decide<G, MODE, i128, AccT>(a, Wi, keys, vals, CAP, lane, active, c, Ki, Sc, sh.k128, sh.d, sh.v, sh.t,
-                                          occ, nocc);
+                                          occ, nocc, i);
 
     if (a.learn && active && lane == 0) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
@@ -703,7 +706,7 @@ __device__ __forceinline__ void move_lanes(const MoveArgs& a, const int32_t* __r
         const KeyT key = (KeyT)Wi * kd[u] - (KeyT)Ki * sd[u];
         if (bd == EMPTY_KEY || better(key, dd[u], bk, bd)) { bk = key; bd = dd[u]; bv = kd[u]; }
     }
-    Decision dcs = finish_decision<MODE, KeyT>(a, Wi, active, c, Ki, Best<KeyT>{bk, bd, bv, kic, nd}, Sc);
+    Decision dcs = finish_decision<MODE, KeyT>(a, Wi, active, i, c, Ki, Best<KeyT>{bk, bd, bv, kic, nd}, Sc);
 
     if (a.learn && active) note_evaluation(a, i, dcs);
     if constexpr (MODE == M_SYNC) {
@@ -758,10 +761,12 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_move_lds(MoveArgs a, cons
 // Buckets 0..3 (all 256-thread blocks) in one launch: block ranges
 // [blk_pre[b], blk_pre[b+1]) belong to bucket b; the tables live in dynamic
 // LDS sized for the largest of the four.
-// Six waves per SIMD fit the 64-bit variants without spilling (the default
-// allocation leaves five); the 128-bit variants keep the compiler's choice.
+// Six waves per SIMD fit the unit-weight 64-bit variants in registers (the
+// default allocation leaves five); weighted variants would spill to scratch
+// memory at six (the weighted 4096^2 grid runs 22% faster at five), so they
+// and the 128-bit variants keep the compiler's choice.
 template <typename OffT, int WK, typename AccT, int MODE, bool WIDE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 6, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((WIDE || WK != 0) ? 1 : 6, 8)))
 k_move_fused(MoveArgs a, FusedLists f) {
     extern __shared__ __align__(16) char dyn[];
     __shared__ MoveShm sh;
@@ -936,7 +941,7 @@ __device__ __forceinline__ void hub_finish(const MoveArgs& a, int32_t h, int32_t
     const i64 Ki = a.K[v];
     const int32_t gv = a.gid ? a.gid[v] : -1;
     const i64 Wv = gv >= 0 ? (i64)a.Wg[gv] : a.W;
-    Decision dcs = finish_decision<MODE, KeyT>(a, Wv, true, c, Ki, b, ld_s<MODE>(&a.Sig[c]));
+    Decision dcs = finish_decision<MODE, KeyT>(a, Wv, true, v, c, Ki, b, ld_s<MODE>(&a.Sig[c]));
     if (lane == 0) {
         a.hub_cnt[h] = 0;
         if constexpr (MODE == M_SYNC) {

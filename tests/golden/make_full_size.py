@@ -16,6 +16,11 @@ on graphs from the seeded generators -- and stored as digests:
                          of the 4096 and every 128th one), SYNC mode, each
                          graph run alone: membership digest, passes,
                          iterations, communities and exact modularity.
+  sbm_fullrange_async.json  the same sample, ASYNC (sequential) mode: the
+                         modularity the oracle reaches in the identity
+                         vertex order and in 8 seeded relabellings
+                         (oracle/orders.py), whose minimum less 0.002 is the
+                         per-graph quality floor of batched ASYNC runs.
 
 Digests are over the arrays' little-endian bytes.  Run from the repository
 root: python tests/golden/make_full_size.py
@@ -94,8 +99,32 @@ def sbm_fullrange():
             "graphs": graphs}
 
 
+def sbm_fullrange_async():
+    from oracle.orders import oracle_q_orders
+    specs = gg.sbm_batch_specs(4096, 200_000)
+    ns = np.array([s[0] for s in specs])
+    pick = sorted(set(np.argsort(ns)[-4:].tolist()) | set(range(0, 4096, 128)))
+
+    def one(k):
+        g = gg.sbm_batch_graph(specs[k])
+        qs = oracle_q_orders(g)
+        return {"index": int(k), "n": int(g.n), "nnz": int(g.nnz), "q_orders": [float(q) for q in qs],
+                "floor": float(min(qs)) - 0.002}
+
+    t = time.time()
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        graphs = list(ex.map(one, pick))
+    print(f"SBM full-range sample, ASYNC orders: {len(graphs)} graphs, {time.time() - t:.0f}s")
+    return {"recipe": "graphgen.sbm_batch_specs(4096, 200000), sequential (ASYNC) oracle in the identity order "
+                      "and 8 relabellings (oracle.orders.oracle_q_orders), library defaults",
+            "graphs": graphs}
+
+
 def main():
-    which = sys.argv[1:] or ["rmat22", "sbm"]
+    which = sys.argv[1:] or ["rmat22", "sbm", "sbm_async"]
+    if "sbm_async" in which:
+        with open(os.path.join(HERE, "sbm_fullrange_async.json"), "w") as f:
+            json.dump(sbm_fullrange_async(), f, indent=1)
     if "sbm" in which:
         with open(os.path.join(HERE, "sbm_fullrange_sync.json"), "w") as f:
             json.dump(sbm_fullrange(), f, indent=1)
