@@ -523,6 +523,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-pruner leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-SBM leg")
     ap.add_argument("--no-autotune", action="store_true", help="skip the degree-bucket autotuner leg")
+    ap.add_argument("--no-device-loop", action="store_true", help="skip the device-driven iterations leg")
     ap.add_argument("--handoff", action="store_true",
                     help="also run the late-pass handoff study (GPU vs OpenMP host after each pass)")
     ap.add_argument("--ablations", action="store_true",
@@ -612,7 +613,9 @@ def main():
     L.close()
     del L
     torch.cuda.empty_cache()
-    devloop = device_loop_leg(lv, torch, (off, idx, w), nnz, mode, args.aux_steps, dt, q, st)
+    devloop = None
+    if not args.no_device_loop:
+        devloop = device_loop_leg(lv, torch, (off, idx, w), nnz, mode, args.aux_steps, dt, q, st)
     ablations = ablation_leg(lv, torch, (off, idx, w), nnz, mode, args.aux_steps) if args.ablations else None
     handoff = handoff_leg(lv, torch, (off, idx, w), nnz, mode, dt, st.passes, args.aux_steps) if args.handoff else None
     learned = wts = None
