@@ -121,6 +121,13 @@ __device__ __forceinline__ int32_t group_bcast(int32_t v, int32_t* s_x) {
 }
 
 // ------------------------------------------------------------ pass init
+// The level's largest weighted degree: one atomic per block whose maximum
+// exceeds the value already there (read first), so that millions of blocks do
+// not serialise on the one address.
+__device__ __forceinline__ void raise_kmax(Ctl* ctl, u64 m) {
+    if (m > __hip_atomic_load(&ctl->kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&ctl->kmax, m);
+}
+
 // Degree bucket of every vertex; C' = identity.  K' = Sigma' = 0, to be
 // filled by the row sums -- except for unit weights (UNIT), where the row
 // sum is the degree and is written here together with its maximum.
@@ -148,7 +155,7 @@ __global__ void __launch_bounds__(256) k_classify(const OffT* __restrict__ off, 
     }
     if (UNIT) {
         __syncthreads();
-        if (threadIdx.x == 0 && s_max) atomicMax(&ctl->kmax, s_max);
+        if (threadIdx.x == 0 && s_max) raise_kmax(ctl, s_max);
     }
 }
 
@@ -195,7 +202,7 @@ __global__ void __launch_bounds__(G > 256 ? G : 256) k_rowsum(Graph<OffT, WK> g,
         atomicMax(&s_max, (u64)s);
     }
     __syncthreads();
-    if (threadIdx.x == 0 && s_max) atomicMax(&ctl->kmax, s_max);
+    if (threadIdx.x == 0 && s_max) raise_kmax(ctl, s_max);
 }
 
 // Static position of each hub and its table capacity: next power of two >=
