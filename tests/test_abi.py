@@ -134,6 +134,17 @@ def test_create_rejects_bad_arguments_before_device_access(lib):
     bad = lv.louvain_params_default()
     bad.mode = 7
     assert _create_status(g, bad)[0] == lv.LOUVAIN_ERR_INVALID
+    bad = lv.louvain_params_default()
+    bad.device_loop = 2
+    assert _create_status(g, bad)[0] == lv.LOUVAIN_ERR_INVALID         # device_loop is 0 or 1
+    bad.device_loop = 1
+    bad.pruner = lv.PRUNE_LEARNED
+    bad.pruner_weights = fake
+    assert _create_status(g, bad)[0] == lv.LOUVAIN_ERR_INVALID         # not with the learned pruner
+    assert "device_loop" in lv.louvain_last_error(None)
+    ok = lv.louvain_params_default()
+    ok.device_loop = 1
+    assert _create_status(g, ok, None, 0)[0] == lv.LOUVAIN_ERR_WORKSPACE  # accepted; no workspace
     assert _create_status(g, p, None, 0)[0] == lv.LOUVAIN_ERR_WORKSPACE  # no workspace
     assert _create_status(g, p, fake + 8, 1 << 40)[0] == lv.LOUVAIN_ERR_WORKSPACE  # misaligned
     assert "256-byte" in lv.louvain_last_error(None)
