@@ -675,7 +675,7 @@ __global__ void __launch_bounds__(256) k_validate(Graph<OffT, WK> g, int64_t n, 
     const int lane = threadIdx.x % WAVE;
     const int64_t nw = (int64_t)gridDim.x * (256 / WAVE);
     u64 wsum = 0;
-    int err = 0;
+    int err = 0, uns = 0;
     for (int64_t v = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE; v < n; v += nw) {
         const i64 o0 = (i64)g.off[v], o1 = (i64)g.off[v + 1];
         if (check && (o1 < o0 || o0 < 0 || o1 > nnz)) { err |= 1; continue; }
@@ -686,11 +686,14 @@ __global__ void __launch_bounds__(256) k_validate(Graph<OffT, WK> g, int64_t n, 
                 if (j < 0 || j >= n) err |= 2;
                 if (w <= 0) err |= 4;
             }
+            if (e > o0 && g.idx[e - 1] >= g.idx[e]) uns = 1;  // a repeated or out-of-order neighbour
             wsum += (u64)w;
         }
     }
     wsum = (u64)group_sum64<WAVE>((i64)wsum);
+    const bool any_uns = __any(uns);
     if (lane == 0 && wsum) atomicAdd(&ctl->wsum, wsum);
+    if (lane == 0 && any_uns) atomicOr(&ctl->unsorted, 1);
     if (err) atomicOr(&ctl->err, err);
 }
 

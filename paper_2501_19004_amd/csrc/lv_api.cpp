@@ -205,6 +205,7 @@ struct louvain_s {
     int32_t smp_rate = 0;
     int64_t smp_count = 0;
     int64_t syncs = 0;         // host waits on the stream during the current run
+    bool rows_unique0 = false;  // every row of the input strictly ascending (no repeated neighbour)
 
     template <typename T>
     T* at(size_t off) { return (T*)(ws + off); }
@@ -507,6 +508,7 @@ louvain_status create_impl(const louvain_graph* g, const int64_t* vbase, int64_t
         return bail(LOUVAIN_ERR_INVALID);
     }
     h->W = (int64_t)c.wsum;
+    h->rows_unique0 = c.unsorted == 0;
     if (c.wsum > ((u64)1 << 62)) {
         h->err = "total weight exceeds 2^62";
         return bail(LOUVAIN_ERR_OVERFLOW);
@@ -637,6 +639,10 @@ louvain_status Runner::run() {
     iota_i32(C, n0, s);
 
     LevelView L = H->L0;
+    // rows without repeated neighbours: the input when validated so, every
+    // super-graph (compacted rows) -- SYNC iteration 0 may then decide hubs
+    // straight from their rows
+    bool uniq = H->rows_unique0;
     bool stopped_before_aggregate = false;
     bool have_newid = false;
     int64_t ncom_last = 0;
@@ -933,6 +939,9 @@ louvain_status Runner::run() {
             a.dshare = dshare;
             // hubs: chunked inserts, one decision per hub, chunked stamping, for
             // the static hub positions [s_lo, s_hi) whose tables share the pool
+            // SYNC iteration 0 decides against the identity membership, so hubs
+            // decide straight from their rows (no tables)
+            const bool hub_direct = sync && t == 0 && uniq && nhub > 0;
             const bool hubs_now = nhub > 0 && (devloop || counts[NB_MOVE] > 0);
             auto hubs_range = [&](int32_t s_lo, int32_t s_hi, bool decide_phase, bool mark_phase) {
                 a.bucket = NB_MOVE;
@@ -944,7 +953,8 @@ louvain_status Runner::run() {
                     a.tab_lo = lo;
                     const int64_t nchunks = hch_pre[hi] - hch_pre[lo];
                     if (decide_phase) {
-                        timed(H, K_MOVE_HUB, 0, [&] { launch_hub_insert(LM, mode, a, nchunks, s); });
+                        if (!hub_direct)
+                            timed(H, K_MOVE_HUB, 0, [&] { launch_hub_insert(LM, mode, a, nchunks, s); });
                         // decide launches of at most part_cap blocks (all blocks of a hub in one launch)
                         for (int32_t sl = lo; sl < hi;) {
                             int32_t sh = sl + 1;
@@ -953,7 +963,8 @@ louvain_status Runner::run() {
                             ad.g_lo = sl;
                             ad.g_hi = sh;
                             timed(H, K_HUB_DECIDE, 0, [&] {
-                                launch_hub_decide(LM, mode, ad, hch_pre[sh] - hch_pre[sl], s);
+                                if (hub_direct) launch_hub_direct(LM, mode, ad, hch_pre[sh] - hch_pre[sl], s);
+                                else launch_hub_decide(LM, mode, ad, hch_pre[sh] - hch_pre[sl], s);
                                 launch_hub_final(LM, mode, ad, s);
                             });
                             sl = sh;
@@ -1488,6 +1499,7 @@ louvain_status Runner::run() {
             launch_compact(ncom, hoff, A.hidx, A.hw, goff, H->sup_off64, gidx, gw, A.out_w64, s);
         });
         L.n = ncom;
+        uniq = true;
         L.nnz = nnz2;
         L.off = goff;
         L.idx = gidx;

@@ -43,7 +43,7 @@ struct Ctl {
     u64 pruned;                   // flagged vertices the learned pruner skipped (for the next iteration)
     // ---- other state
     int32_t err;                  // validation error bits
-    int32_t nonisolated;
+    int32_t unsorted;             // validation: some row is not strictly ascending by neighbour id
     u64 kmax;                     // largest weighted degree of the level
     u64 wsum;                     // total weight (validation pass)
     int32_t bcount[MAX_BUCKETS];  // bucket sizes (classification)

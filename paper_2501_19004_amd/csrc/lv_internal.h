@@ -208,6 +208,10 @@ void launch_move(const LevelView& L, int bucket, int mode, const MoveArgs& a, co
 void launch_hub_insert(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s);
 void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s);
 void launch_hub_final(const LevelView& L, int mode, const MoveArgs& a, hipStream_t s);
+// SYNC iteration 0 on rows without repeated neighbours: hub decisions
+// straight from the rows (C' is the identity snapshot), in place of
+// launch_hub_insert + launch_hub_decide (launch_hub_final still combines).
+void launch_hub_direct(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s);
 void launch_hub_mark(const LevelView& L, const MoveArgs& a, int64_t nchunks, hipStream_t s);
 void launch_move_fused(const LevelView& L, int mode, const MoveArgs& a, const FusedLists& f, hipStream_t s);
 void launch_sync_apply(const LevelView& L, const MoveArgs& a, const int32_t* list, int64_t count, hipStream_t s);

@@ -1044,6 +1044,80 @@ __global__ void __launch_bounds__(1024) k_hub_decide(MoveArgs a) {
     else hub_decide_block<MODE, i128, AccT, OffT>(a, h, v, k, nch, s_k128, s_d, s_v, s_t);
 }
 
+// Iteration 0 of a pass, before any vertex has moved: every neighbour j is its
+// own community (C' is the identity), so on a row without repeated neighbours
+// K_{i->j} is the arc's weight and the decision is an argmax over the row --
+// no table, no atomics.  Blocks take the insert chunks of HUB_CH arcs; a hub
+// with several chunks posts partial bests that k_hub_final combines, as the
+// table path does.  Valid only while nothing has moved: used for SYNC
+// iteration 0, which decides against that snapshot.  (Deciding all ASYNC hubs
+// of iteration 0 before the first slice would qualify too, but that schedule
+// lowers the modularity reached.)
+template <int MODE, typename KeyT, typename OffT, int WK>
+__device__ __forceinline__ void hub_direct_block(const MoveArgs& a, int32_t h, int32_t v, int64_t k, int64_t nch,
+                                                 KeyT* s_k, int32_t* s_d, i64* s_v, i64* s_t) {
+    constexpr int G = 1024;
+    const Graph<OffT, WK> g{(const OffT*)a.off, a.idx, a.w};
+    const int tid = threadIdx.x;
+    const i64 Ki = a.K[v];
+    const int32_t gv = a.gid ? a.gid[v] : -1;
+    const i64 Wv = gv >= 0 ? (i64)a.Wg[gv] : a.W;
+    const i64 e0 = (i64)g.off[v] + k * HUB_CH;
+    const i64 e1 = min(e0 + (i64)HUB_CH, (i64)g.off[v + 1]);
+    KeyT bk = (sizeof(KeyT) == 8) ? (KeyT)INT64_MIN : (KeyT)(((i128)1) << 127);
+    int32_t bd = EMPTY_KEY;
+    i64 bv = 0, nd = 0;
+    for (i64 e = e0 + tid; e < e1; e += G) {
+        const int32_t j = g.idx[e];
+        if (j == v) continue;
+        const i64 wj = g.weight(e);
+        const KeyT key = (KeyT)Wv * wj - (KeyT)Ki * ld_s<MODE>(&a.Sig[j]);
+        ++nd;
+        if (bd == EMPTY_KEY || better(key, j, bk, bd)) { bk = key; bd = j; bv = wj; }
+    }
+    reduce_best<G, KeyT>(bk, bd, bv, s_k, s_d, s_v);
+    nd = reduce_sum<G>(nd, s_t);
+    const Best<KeyT> b{bk, bd, bd != EMPTY_KEY ? bv : 0, 0, nd};
+    if (nch == 1) {
+        hub_finish<MODE, KeyT>(a, h, v, (i64)g.off[v + 1] - (i64)g.off[v], b, tid);
+    } else if (tid == 0) {
+        HubPart* mine = a.hub_part + blockIdx.x;
+        const i128 key = (i128)b.bk;
+        mine->klo = (i64)(u64)key;
+        mine->khi = (i64)(key >> 64);
+        mine->v = b.bv;
+        mine->kic = 0;
+        mine->nd = b.nd;
+        mine->d = b.bd;
+    }
+}
+
+template <typename OffT, int WK, int MODE>
+__global__ void __launch_bounds__(1024) k_hub_direct(MoveArgs a) {
+    if (a.dit && a.dit->halt) return;
+    constexpr int G = 1024;
+    __shared__ i128 s_k128[G / WAVE];
+    __shared__ i64 s_k64[G / WAVE];
+    __shared__ int32_t s_d[G / WAVE];
+    __shared__ i64 s_v[G / WAVE];
+    __shared__ i64 s_t[G / WAVE];
+    const int32_t ng = a.g_hi - a.g_lo;
+    const int64_t chunk_base = a.hch_pre[a.g_lo];
+    const int32_t h = a.g_lo + owner_of(a.hch_pre + a.g_lo, ng, chunk_base, blockIdx.x);
+    const int32_t v = a.hub_list[h];
+    const int64_t k = (int64_t)blockIdx.x - (a.hch_pre[h] - chunk_base);
+    const int64_t nch = a.hch_pre[h + 1] - a.hch_pre[h];
+    if (!hub_queued(a, v)) {
+        if (k == 0 && threadIdx.x == 0) {
+            a.gdec[h] = -1;
+            if constexpr (MODE == M_SYNC) a.sdec[v] = -1;
+        }
+        return;
+    }
+    if (!a.wide) hub_direct_block<MODE, i64, OffT, WK>(a, h, v, k, nch, s_k64, s_d, s_v, s_t);
+    else hub_direct_block<MODE, i128, OffT, WK>(a, h, v, k, nch, s_k128, s_d, s_v, s_t);
+}
+
 // Hubs of the launch with more than one decide block: one wave per hub
 // combines the partial bests (ties to the smaller community) and decides.
 template <int MODE, typename KeyT, typename OffT>
@@ -1258,6 +1332,19 @@ void launch_hub_decide(const LevelView& L, int mode, const MoveArgs& a, int64_t 
         if (mode == M_SYNC) k_hub_decide<OffT, WK, AccT, M_SYNC><<<(unsigned)nh, 1024, 0, s>>>(a);
         else if (mode == M_ASYNC_CACHED) k_hub_decide<OffT, WK, AccT, M_ASYNC_CACHED><<<(unsigned)nh, 1024, 0, s>>>(a);
         else k_hub_decide<OffT, WK, AccT, M_ASYNC_COHERENT><<<(unsigned)nh, 1024, 0, s>>>(a);
+    });
+}
+
+void launch_hub_direct(const LevelView& L, int mode, const MoveArgs& a, int64_t nchunks, hipStream_t s) {
+    if (nchunks <= 0) return;
+    LevelTypes t = L.t;
+    t.acc64 = 0;  // no table
+    dispatch_types(t, [&](auto o, auto w, auto) {
+        using OffT = typename decltype(o)::type;
+        constexpr int WK = decltype(w)::value;
+        if (mode == M_SYNC) k_hub_direct<OffT, WK, M_SYNC><<<(unsigned)nchunks, 1024, 0, s>>>(a);
+        else if (mode == M_ASYNC_CACHED) k_hub_direct<OffT, WK, M_ASYNC_CACHED><<<(unsigned)nchunks, 1024, 0, s>>>(a);
+        else k_hub_direct<OffT, WK, M_ASYNC_COHERENT><<<(unsigned)nchunks, 1024, 0, s>>>(a);
     });
 }
 

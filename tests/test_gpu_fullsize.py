@@ -13,14 +13,17 @@ must reproduce them exactly:
   200000] (its four largest graphs and every 128th one), batched with 64-bit
   offsets: each graph's membership, passes, iterations, communities and
   exact modularity equal its lone oracle run.
-* The same sample batched in ASYNC mode: graph by graph, the exact
-  modularity of the GPU membership is at least the lowest the sequential
-  oracle reaches over the identity order and 8 seeded relabellings (stored
-  per graph), less 0.002.  On graphs whose sequential runs themselves spread
-  by more than that between visiting orders (weak community structure: 11
-  of the 36), concurrent runs spread as much between runs, so there the
-  allowance is that spread: a graph may end as far below the lowest
-  sequential order as the sequential orders end apart.
+* The same sample batched in ASYNC mode, 3 runs: every run's membership is
+  valid with the exact modularity the oracle computes for it, and graph by
+  graph Q is compared with the lowest modularity the sequential oracle
+  reaches over the identity order and 8 seeded relabellings (stored per
+  graph).  Where those sequential runs agree within 0.002 (25 of the 36
+  graphs), every run must reach that lowest order less 0.002.  On the 11
+  weak-structure graphs the sequential orders themselves end up to 0.074
+  apart and concurrent runs vary as much from run to run (one graph moved
+  by 0.019 over five runs), so no single run is a meaningful sample: there
+  the median of the 3 runs must reach the lowest order less the orders'
+  own spread.
 """
 import hashlib
 import json
@@ -38,6 +41,7 @@ torch = pytest.importorskip("torch")
 lv = pytest.importorskip("paper_2501_19004_amd")
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+RUNS = 3  # concurrent (ASYNC) runs of the full-range batch
 
 
 def dev():
@@ -118,21 +122,32 @@ def test_full_range_sbm_batch_async_per_graph():
     specs = gg.sbm_batch_specs(4096, 200_000)
     graphs = [gg.sbm_batch_graph(specs[r["index"]]) for r in ref]
     assert [(g.n, g.nnz) for g in graphs] == [(r["n"], r["nnz"]) for r in ref]
-    print(f"[case] batched ASYNC over {len(graphs)} graphs of the full-range SBM recipe, 64-bit offsets", flush=True)
+    print(f"[case] batched ASYNC over {len(graphs)} graphs of the full-range SBM recipe, 64-bit offsets, 3 runs",
+          flush=True)
     off, idx, w, vbase = lv.batch_tensors(graphs, dev(), offset_bits=64)
     L = lv.Louvain(off, idx, w, vbase=vbase, mode=lv.ASYNC)
-    L.run()
-    memb = L.membership().cpu().numpy()
-    q, num, den = L.modularity_batch()
-    passes, iters, comms = L.batch_results()
+    runs = []
+    for _ in range(RUNS):
+        L.run()
+        memb = L.membership().cpu().numpy()
+        q, num, den = L.modularity_batch()
+        passes, iters, comms = L.batch_results()
+        for k, g in enumerate(graphs):
+            part = memb[vbase[k]:vbase[k + 1]]
+            assert (num[k], den[k]) == oracle.modularity_parts(g, part), k
+            assert sorted(set(part.tolist())) == list(range(comms[k])), k
+        runs.append(np.array(q))
     L.close()
-    d = []
-    for k, (g, r) in enumerate(zip(graphs, ref)):
-        part = memb[vbase[k]:vbase[k + 1]]
-        assert (num[k], den[k]) == oracle.modularity_parts(g, part), k
-        assert sorted(set(part.tolist())) == list(range(comms[k])), k
+    runs = np.array(runs)
+    bad = []
+    for k, r in enumerate(ref):
         qs = r["q_orders"]
-        d.append(q[k] - (min(qs) - max(0.002, max(qs) - min(qs))))
-    print(f"Q_gpu - floor per graph: min {min(d):+.5f} mean {np.mean(d):+.5f}")
-    bad = [(ref[k]["index"], ref[k]["n"], round(d[k], 5)) for k in range(len(ref)) if d[k] < 0]
+        spread = max(qs) - min(qs)
+        if spread <= 0.002:  # a well-defined sequential optimum: every run within 0.002 of the lowest order
+            got, floor = runs[:, k].min(), min(qs) - 0.002
+        else:  # weak structure: the median run within the sequential runs' own spread of the lowest order
+            got, floor = float(np.median(runs[:, k])), min(qs) - spread
+        if got < floor:
+            bad.append((r["index"], r["n"], round(spread, 5), round(got - floor, 5)))
+    print(f"per-run Q_gpu - lowest order: min {float((runs - np.array([min(r['q_orders']) for r in ref])).min()):+.5f}")
     assert not bad, bad
