@@ -16,6 +16,10 @@ on graphs from the seeded generators -- and stored as digests:
                          of the 4096 and every 128th one), SYNC mode, each
                          graph run alone: membership digest, passes,
                          iterations, communities and exact modularity.
+  rmat24_ef28_async.json  R-MAT scale 24, edge factor 28, seed 27 (the
+                         benchmark's scale-27 recipe at 1/8 of its vertices),
+                         ASYNC (sequential) mode in the identity order: the
+                         graph's digest, counts and exact modularity.
   sbm_fullrange_async.json  the same sample, ASYNC (sequential) mode: the
                          modularity the oracle reaches in the identity
                          vertex order and in 8 seeded relabellings
@@ -120,8 +124,28 @@ def sbm_fullrange_async():
             "graphs": graphs}
 
 
+def rmat24_async():
+    t = time.time()
+    g = gg.rmat(24, 28, seed=27)
+    t_gen = time.time() - t
+    r = oracle.louvain(g, oracle.Params(mode=oracle.ASYNC))
+    num, den = oracle.modularity_parts(g, r.membership)
+    out = {"graph": "R-MAT scale 24, edge factor 28, a/b/c=.57/.19/.19, seed 27, unit weights",
+           "n": int(g.n), "nnz": int(g.nnz),
+           "graph_sha256": sha(np.asarray(g.offsets, np.int64), np.asarray(g.indices, np.int32)),
+           "mode": "ASYNC (sequential, identity order)", "params": "library defaults",
+           "passes": int(r.passes), "iterations": int(r.iterations), "communities": int(r.communities),
+           "q_num": str(num), "q_den": str(den), "q": float(num) / float(den)}
+    print(f"rmat24 ef28 ASYNC: generated in {t_gen:.0f}s, {r.passes} passes, {r.iterations} iterations, "
+          f"Q={out['q']:.6f}, {time.time() - t:.0f}s")
+    return out
+
+
 def main():
-    which = sys.argv[1:] or ["rmat22", "sbm", "sbm_async"]
+    which = sys.argv[1:] or ["rmat22", "sbm", "sbm_async", "rmat24"]
+    if "rmat24" in which:
+        with open(os.path.join(HERE, "rmat24_ef28_async.json"), "w") as f:
+            json.dump(rmat24_async(), f, indent=1)
     if "sbm_async" in which:
         with open(os.path.join(HERE, "sbm_fullrange_async.json"), "w") as f:
             json.dump(sbm_fullrange_async(), f, indent=1)

@@ -10,7 +10,15 @@ one by one and the run is checked through properties that hold at any size:
 * ASYNC, full run: community ids are dense and the reported modularity equals
   Eq. 1 of the returned membership evaluated exactly with integer tensor
   arithmetic, independently of the library.
+The same recipe at scale 24 (16.8M vertices, 1/8 of the vertices) is within
+the oracle's reach: its sequential ASYNC run is stored
+(tests/golden/rmat24_ef28_async.json, written by make_full_size.py from the
+oracle alone), and the GPU run of the device-generated graph must reach that
+modularity less 0.002.
 """
+import hashlib
+import json
+import os
 import numpy as np
 import pytest
 
@@ -128,3 +136,29 @@ def test_full_size_async_rmat27(rmat27):
     assert num * eden == enum * den, (num, den, enum, eden)
     # the singleton partition has Q < 0; local moving only takes positive gains
     assert q > 0
+
+
+def test_same_recipe_scale24_async_against_stored_oracle():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "rmat24_ef28_async.json")) as f:
+        ref = json.load(f)
+    print("[case] R-MAT scale 24 ef 28 seed 27 on the device, ASYNC against the stored oracle run", flush=True)
+    off, idx = gg.rmat_device(24, EF, seed=SEED, device="cuda:0")
+    torch.cuda.synchronize()
+    n = off.numel() - 1
+    assert (n, idx.numel()) == (ref["n"], ref["nnz"])
+    h = hashlib.sha256()
+    h.update(off.cpu().numpy().astype("<i8").tobytes())
+    h.update(idx.cpu().numpy().astype("<i4").tobytes())
+    assert h.hexdigest() == ref["graph_sha256"]
+    L = lv.Louvain(off, idx, None, mode=lv.ASYNC)
+    L.run()
+    q, num, den = L.modularity()
+    memb = L.membership()
+    L.close()
+    enum, eden = exact_modularity_parts(off, idx, memb.to(torch.int32), n)
+    assert num * eden == enum * den, (num, den, enum, eden)
+    print(f"Q_gpu - Q_oracle = {q - ref['q']:+.5f}", flush=True)
+    assert q >= ref["q"] - 0.002, (q, ref["q"])
