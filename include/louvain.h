@@ -143,7 +143,7 @@ typedef struct {
     /* LEARNED pruner only: exit test of a sweep (0 strict, the default: no
      * positive-gain move left; 1 tolerance). */
     int32_t guard_tolerance;
-    /* ASYNC only: at least this many queued vertices per slice (default 32);
+    /* ASYNC only: at least this many queued vertices per slice (default 256);
      * an iteration uses min(async_slices, queued / async_slice_min) slices. */
     int32_t async_slice_min;
     /* ASYNC only: the hubs (vertices above the largest LDS bucket) of an

@@ -363,7 +363,7 @@ void louvain_params_default(louvain_params* p) {
     p->async_slices = 64;
     p->async_slice_iters = 0;
     p->guard_tolerance = 0;
-    p->async_slice_min = 32;
+    p->async_slice_min = 256;
     p->async_hub_groups = 32;
     p->async_min_label = 1;
     p->async_interleave = 0;

@@ -87,7 +87,7 @@ def test_learned_entry_points_reject_bad_arguments(lib):
     p = lv.louvain_params_default()
     assert (p.guard_tolerance, p.pruner_weights, p.pruner_threshold) == (0, None, 0.5)
     assert (p.async_coherent, p.async_slices, p.async_slice_min, p.async_hub_groups, p.async_min_label) == \
-        (0, 64, 32, 32, 1)
+        (0, 64, 256, 32, 1)
 
 
 def test_workspace_size_is_host_only_and_monotone(lib):
