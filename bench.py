@@ -50,7 +50,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Louvain M edges/s, plain vs learned-pruned at ΔQ≤0.002; local-move HBM GB/s"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_SOURCES = ["paper_2501_19004_amd/csrc/lv_move.hip", "paper_2501_19004_amd/csrc/lv_common.h",
-                   "paper_2501_19004_amd/csrc/lv_internal.h"]
+                   "paper_2501_19004_amd/csrc/lv_internal.h", "paper_2501_19004_amd/csrc/lv_api.cpp"]
 KERNEL_FILE = {"move_b0_3": "move_fused", "move_b4": "move_lds", "move_hub": "hub"}
 
 
@@ -70,7 +70,8 @@ def kernel_source_digest():
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-    calibration), or None when there is none or the sources changed since."""
+    calibration), or None when there is none or the sources changed since
+    (the kernels' and the host driver's, which sizes the launches)."""
     path = os.path.join(ROOT, "profiles", f"{KERNEL_FILE.get(kernel, kernel)}_{workload}_traffic.md")
     try:
         text = open(path).read()

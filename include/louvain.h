@@ -135,7 +135,9 @@ typedef struct {
     /* ASYNC only: split every iteration into this many sequential launches
      * over consecutive slices of each bucket's queue (sorted by vertex id);
      * later slices see the moves of earlier ones.  1 = one launch per bucket;
-     * default 64. */
+     * default 64.  A single graph's level with more than async_slices x 2^19
+     * queued vertices uses one slice per 2^19 of them, up to twice
+     * async_slices, and scales async_hub_groups alike. */
     int32_t async_slices;
     /* ASYNC only: apply async_slices to the first this-many iterations of
      * every pass (0 = to every iteration). */

@@ -34,6 +34,12 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 constexpr size_t ALIGN = 256;
+// ASYNC slices of a huge single-graph level hold at most this many queued
+// vertices (measured on R-MAT 27: 128 slices with 64 hub groups ran 4.5 %
+// faster at higher modularity than 64 with 32; levels of a few million
+// vertices keep async_slices, where more slices only add launches).
+constexpr int64_t SLICE_SPAN = 1 << 19;
+
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 inline uint64_t next_pow2(uint64_t x) {
@@ -62,7 +68,8 @@ bool make_layout(int64_t n, int64_t m, int64_t count, int slices, Layout* L) {
     const size_t N = (size_t)n, M = (size_t)m;
     L->ctl = take(sizeof(Ctl));
     L->dit = take(sizeof(DevIter));
-    L->dshare = take((size_t)NB_MOVE * std::max(1, slices) * 8);  // slice table of device-driven iterations
+    // slice table of device-driven iterations (a huge level may use up to twice `slices`)
+    L->dshare = take((size_t)NB_MOVE * 2 * std::max(1, slices) * 8);
     L->seg = take(32 * sizeof(int64_t));
     L->C = take(N * 4);
     L->Cp = take(N * 4);
@@ -783,8 +790,13 @@ louvain_status Runner::run() {
         // the pass's first queue, for every iteration of the pass)
         auto slices_of = [&](int t, int64_t queued) {
             const bool slice_now = P.async_slice_iters <= 0 || t < P.async_slice_iters;
-            const int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
-            return (int)std::max<int64_t>(1, std::min<int64_t>(ns, queued / std::max(1, P.async_slice_min)));
+            int ns = (!sync && P.async_slices > 1 && slice_now) ? P.async_slices : 1;
+            ns = (int)std::max<int64_t>(1, std::min<int64_t>(ns, queued / std::max(1, P.async_slice_min)));
+            // a huge single-graph level: at most SLICE_SPAN queued vertices per
+            // slice, up to twice async_slices (batched graphs are small)
+            if (!batch && ns > 1 && ns == P.async_slices)
+                ns = (int)std::min<int64_t>(2 * (int64_t)P.async_slices, std::max<int64_t>(ns, queued / SLICE_SPAN));
+            return ns;
         };
         auto interleaved = [&](int ns) { return !sync && P.async_interleave && ns > 1 ? 1 : 0; };
         if (devloop) {
@@ -984,7 +996,12 @@ louvain_status Runner::run() {
             const int ns = slices_of(t, queued);
             // hub groups: group k covers the static hub positions [k*nhub/hg, (k+1)*nhub/hg)
             // and runs with slice due(k) = (k+1)*ns/hg - 1
-            const int hg = (!sync && P.async_hub_groups > 0) ? std::min(P.async_hub_groups, ns) : ns;
+            // (a level with more slices than async_slices scales its hub groups alike)
+            const int hg = (!sync && P.async_hub_groups > 0)
+                               ? (int)std::min<int64_t>(ns, ns > P.async_slices
+                                                                ? (int64_t)P.async_hub_groups * ns / P.async_slices
+                                                                : P.async_hub_groups)
+                               : ns;
             // batched ASYNC: slice sl takes the sl-th share of every graph's part
             // of each bucket's queue (graphs are contiguous id ranges, so plain
             // contiguous slices would hold whole graphs)
