@@ -176,8 +176,8 @@ typedef struct {
      * the iterations of a pass in chunks (2, 4, 8, ...) with one readback per
      * chunk instead of one per iteration; launches are sized for the pass's
      * largest queue and those after the pass's end return at once.  ASYNC
-     * slices: every iteration of a pass uses the slice count of its first
-     * (min(async_slices, nonisolated / async_slice_min)).  Results: SYNC as
+     * slices: every iteration of a pass uses the slice count of its first,
+     * counted on the vertices with arcs (see async_slices).  Results: SYNC as
      * with 0.  Not with the LEARNED pruner, sample recording or an
      * iteration trace (LOUVAIN_ERR_INVALID).  0 = host-driven (default). */
     int32_t device_loop;
